@@ -1,0 +1,156 @@
+/*
+ * stp.h -- C ABI of the element-local space-time predictor of ADER-DG for
+ * Biot poroelasticity, solved by block-wise back-substitution over the
+ * spatial-degree blocks (Wolf et al., "An Efficient ADER-DG Local Time
+ * Stepping Scheme for 3D HPC Simulation of Seismic Waves in Poroelastic
+ * Media", arXiv 2108.10565).  Kernels are written for AMD MI355X (gfx950).
+ *
+ * What one call computes, per element (section "Space-Time predictor",
+ * eq:stp-lineq / eq:linear_system, solved as in section "Block-wise
+ * back-substitution", Algorithm 3):
+ *
+ *   ( d_pq W_rs M_kl - d_pq K^tau_rs M_kl - E*_pq S_rs M_kl
+ *     + sum_j A^{j*}_pq S_rs K^j_kl ) Q_qls = d_pq w_r M_kl Q0_ql,
+ *   A^{j*} = dt A^j,  E* = dt E,
+ *
+ * and the time-integrated DOFs Qint_pl = dt * sum_s Q_pls int_0^1 chi_s
+ * = dt * Q_pl0.
+ *
+ * Conventions (part of the ABI):
+ *  - quantities p = 0..12 in the order (sxx, syy, szz, sxy, syz, sxz,
+ *    u, v, w, p, uf, vf, wf) of section "Governing equations";
+ *  - temporal basis chi_s(tau) = P_s(2 tau - 1), s = 0..N (Legendre,
+ *    unnormalised, chi_s(1) = 1) on the reference interval [0, 1];
+ *  - spatial basis: Dubiner polynomials on the reference tetrahedron
+ *    {x, y, z > 0, x + y + z < 1},
+ *      phi_ijk = P_i(a)(1-y-z)^i P_j^(2i+1,0)(b)(1-z)^j P_k^(2i+2j+2,0)(c),
+ *      a = 2x/(1-y-z) - 1, b = 2y/(1-z) - 1, c = 2z - 1,
+ *    unnormalised, ordered by total degree n = i+j+k, then k = 0..n, then
+ *    j = 0..n-k;  B = (N+1)(N+2)(N+3)/6 modes, T = N+1 time modes;
+ *  - all arrays are C-contiguous (row-major), float64.
+ *
+ * Ownership: the caller owns every input, output and workspace buffer.
+ * The library owns only the handle (host memory).  stp_predict allocates
+ * nothing, never synchronises the stream and launches on the stream given.
+ *
+ * Errors: every entry point returns a stp_status and never aborts.  Cheap
+ * argument checks are done on the host before any launch; checks that need
+ * the data are in stp_validate (opt-in, synchronises).  A HIP launch
+ * failure is reported as STP_EHIP with the HIP message in stp_last_error.
+ * A handle must not be used from two host threads at once.
+ */
+#ifndef STP_H
+#define STP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STP_NQ 13          /* quantities of the poroelastic system        */
+#define STP_MAX_DEGREE 7   /* supported polynomial degrees N = 0..7       */
+#define STP_MAX_REFINE 3   /* refinement steps of the mixed-precision path */
+
+typedef struct stp_handle_s* stp_handle;
+
+typedef enum stp_status {
+  STP_OK = 0,
+  STP_EINVAL = -1,      /* bad argument: NULL pointer with n > 0, n < 0,
+                           dt <= 0 or not finite, bad enum or flags       */
+  STP_EDEGREE = -2,     /* degree outside 0..STP_MAX_DEGREE               */
+  STP_ENOTUPPER = -3,   /* (stp_validate) an E has a non-zero strictly
+                           below its diagonal                             */
+  STP_ESINGULAR = -4,   /* (stp_validate) Z - dt E_pp I is singular or
+                           dt E_pp > 0 makes it nearly so                 */
+  STP_ENOMEM = -5,      /* host allocation failed                         */
+  STP_EHIP = -6,        /* HIP runtime error (see stp_last_error)         */
+  STP_EWORKSPACE = -7,  /* workspace smaller than stp_workspace_size      */
+  STP_ENONFINITE = -8   /* (stp_validate) NaN or Inf in an input          */
+} stp_status;
+
+typedef enum stp_precision {
+  /* Algorithm 3 entirely in float64. */
+  STP_FP64 = 0,
+  /* Algorithm 3 in float32 with float32 accumulation (the star x stiffness
+   * x time chain), stiff diagonal-block inverses kept in float64, then
+   * refine_steps rounds of iterative refinement: float64 matrix-free
+   * residual of the full element system, correction by the float32 chain,
+   * float64 update.  Outputs are float64. */
+  STP_FP32_REFINE = 1
+} stp_precision;
+
+/* flags of stp_predict */
+#define STP_FLAG_NONE 0u
+/* Use the one-element-per-workgroup LDS kernel (float64 only) instead of
+ * the fused register-resident kernel.  Same results up to rounding; kept
+ * as an independent GPU implementation and for debugging. */
+#define STP_FLAG_REFERENCE_KERNEL 1u
+
+/* Create / destroy a handle.  No device work is done by either. */
+stp_status stp_create(stp_handle* handle);
+stp_status stp_destroy(stp_handle handle);
+
+/* Bytes of device workspace stp_predict needs for these arguments
+ * (currently 0 for every path: all intermediates live in registers, LDS or
+ * the output buffer Q). */
+stp_status stp_workspace_size(stp_handle handle, int degree, int64_t n_elements,
+                              stp_precision precision, int refine_steps,
+                              size_t* bytes);
+
+/* Predict n_elements independent elements on `hip_stream` (a hipStream_t,
+ * NULL = default stream).  All array pointers are DEVICE pointers, 16-byte
+ * aligned, float64, C-contiguous:
+ *   star [n][3][13][13]  reference-element Jacobians A^1, A^2, A^3
+ *                        (A^j = A dxi_j/dx + B dxi_j/dy + C dxi_j/dz,
+ *                        subsection "Spatial discretisation"), NOT scaled
+ *                        by dt;
+ *   E    [n][13][13]     source matrix, upper triangular (section
+ *                        "Governing equations"), NOT scaled by dt;
+ *                        entries below the diagonal are never read;
+ *   Q0   [n][13][B]      spatial DOFs at the start of the step;
+ *   Q    [n][13][B][T]   out: space-time DOFs;
+ *   Qint [n][13][B]      out: dt * time average over the step; may be NULL.
+ * dt > 0 and finite (one time step for every element of the call).
+ * refine_steps in 0..STP_MAX_REFINE (ignored for STP_FP64).
+ * n_elements == 0 is a no-op returning STP_OK. */
+stp_status stp_predict(stp_handle handle, void* hip_stream, int degree,
+                       int64_t n_elements, double dt, const double* star,
+                       const double* E, const double* Q0, double* Q,
+                       double* Qint, stp_precision precision,
+                       int refine_steps, void* workspace,
+                       size_t workspace_bytes, unsigned flags);
+
+/* Data checks (synchronises `hip_stream`): non-finite input -> STP_ENONFINITE,
+ * a non-zero below the diagonal of some E -> STP_ENOTUPPER, dt E_pp >= 0.5
+ * (the diagonal-block matrices Z - dt E_pp I are then not guaranteed
+ * invertible by the kernels' elimination without pivoting) ->
+ * STP_ESINGULAR.  Returns STP_OK when the inputs are fit for stp_predict. */
+stp_status stp_validate(stp_handle handle, void* hip_stream, int degree,
+                        int64_t n_elements, double dt, const double* star,
+                        const double* E, const double* Q0);
+
+/* Reference matrices the kernels use for degree N, computed on the host by
+ * Gauss quadrature in collapsed coordinates (HOST pointers, for tests):
+ *   Z      [T][T]     S^-1 (W - K^tau)  (section "Block-wise back-substitution")
+ *   Sinv_w [T]        S^-1 w
+ *   Khat   [3][B][B]  M^-1 K^alpha, alpha = xi, eta, zeta
+ * Any pointer may be NULL to skip it. */
+stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z,
+                                  double* Sinv_w, double* Khat);
+
+/* FLOP counts per element: the paper's upper bound of Algorithm 3 (Table
+ * "tab:flop-count"), and the count this library executes in its fused
+ * float64 kernel (useful FLOP: dense star matrices, non-zero Khat entries). */
+stp_status stp_flops(int degree, double* paper_bound, double* executed);
+
+const char* stp_status_string(stp_status status);
+/* Human-readable detail of the last failure on this handle ("" if none). */
+const char* stp_last_error(stp_handle handle);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STP_H */

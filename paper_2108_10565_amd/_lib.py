@@ -1,0 +1,87 @@
+"""ctypes binding of ``libstp.so`` (the C ABI declared in include/stp.h).
+
+Argument marshalling only: every step of the predictor runs in the HIP
+kernels of the library.  PyTorch provides device memory and the stream.
+The binding raises if the library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libstp.so")
+
+STP_OK = 0
+STATUS_NAMES = {0: "STP_OK", -1: "STP_EINVAL", -2: "STP_EDEGREE", -3: "STP_ENOTUPPER",
+                -4: "STP_ESINGULAR", -5: "STP_ENOMEM", -6: "STP_EHIP", -7: "STP_EWORKSPACE",
+                -8: "STP_ENONFINITE"}
+STP_FP64 = 0
+STP_FP32_REFINE = 1
+STP_FLAG_REFERENCE_KERNEL = 1
+MAX_DEGREE = 7
+EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "stp_validate",
+            "stp_reference_matrices", "stp_flops", "stp_status_string", "stp_last_error")
+
+_lib = None
+
+
+class StpError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{name}: {detail}" if detail else name)
+
+
+def load(path: str = LIB_PATH):
+    """Load libstp.so (once) and declare the prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run __graft_entry__.build() or python paper_2108_10565_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    vp, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.stp_create.argtypes = [ctypes.POINTER(vp)]
+    lib.stp_destroy.argtypes = [vp]
+    lib.stp_workspace_size.argtypes = [vp, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(sz)]
+    lib.stp_predict.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
+                                ctypes.c_int, ctypes.c_int, vp, sz, ctypes.c_uint]
+    lib.stp_validate.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp]
+    lib.stp_reference_matrices.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.stp_flops.argtypes = [ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.stp_status_string.argtypes = [ctypes.c_int]
+    lib.stp_status_string.restype = ctypes.c_char_p
+    lib.stp_last_error.argtypes = [vp]
+    lib.stp_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED[:-2]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class Handle:
+    """Owns one stp_handle."""
+
+    def __init__(self):
+        self.lib = load()
+        self.ptr = ctypes.c_void_p()
+        self.check(self.lib.stp_create(ctypes.byref(self.ptr)))
+
+    def check(self, status: int):
+        if status != STP_OK:
+            detail = self.lib.stp_last_error(self.ptr).decode() if self.ptr else ""
+            raise StpError(status, detail)
+
+    def close(self):
+        if self.ptr:
+            self.lib.stp_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,98 @@
+"""Python entry points with the same names as the C ABI (include/stp.h)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+_handle = None
+
+
+def _h():
+    global _handle
+    if _handle is None:
+        _handle = _lib.Handle()
+    return _handle
+
+
+def n_modes(N: int) -> int:
+    return (N + 1) * (N + 2) * (N + 3) // 6
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+_PREC = {"fp64": _lib.STP_FP64, "fp32_refine": _lib.STP_FP32_REFINE}
+
+
+def workspace_size(degree: int, n: int, precision: str = "fp64", refine_steps: int = 1) -> int:
+    h = _h()
+    out = ctypes.c_size_t()
+    h.check(h.lib.stp_workspace_size(h.ptr, degree, n, _PREC[precision], refine_steps,
+                                     ctypes.byref(out)))
+    return out.value
+
+
+def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine_steps: int = 1,
+            Q=None, Qint=None, with_qint: bool = True, reference_kernel: bool = False,
+            stream=None):
+    """Space-time DOFs Q [n,13,B,T] and time-integrated DOFs Qint [n,13,B].
+
+    Q0 [n,13,B], star [n,3,13,13], E [n,13,13]: float64, contiguous, on the
+    same cuda device.  Outputs are allocated here unless passed in.  The call
+    is asynchronous on ``stream`` (default: torch's current stream)."""
+    import torch
+    h = _h()
+    n = int(Q0.shape[0])
+    B, T = n_modes(degree), degree + 1
+    for name, t, shape in (("Q0", Q0, (n, 13, B)), ("star", star, (n, 3, 13, 13)), ("E", E, (n, 13, 13))):
+        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: expected contiguous cuda float64 {shape}, got "
+                             f"{tuple(t.shape)} {t.dtype} cuda={t.is_cuda}")
+    if Q is None:
+        Q = torch.empty((n, 13, B, T), dtype=torch.float64, device=Q0.device)
+    if Qint is None and with_qint:
+        Qint = torch.empty((n, 13, B), dtype=torch.float64, device=Q0.device)
+    ws = workspace_size(degree, n, precision, refine_steps)
+    work = torch.empty(ws, dtype=torch.uint8, device=Q0.device) if ws else None
+    if stream is None:
+        stream = torch.cuda.current_stream(Q0.device)
+    flags = _lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0
+    h.check(h.lib.stp_predict(h.ptr, ctypes.c_void_p(stream.cuda_stream), degree, n, float(dt),
+                              _ptr(star), _ptr(E), _ptr(Q0), _ptr(Q), _ptr(Qint), _PREC[precision],
+                              refine_steps, _ptr(work), ws, flags))
+    return Q, Qint
+
+
+def validate(Q0, star, E, dt: float, degree: int, stream=None) -> None:
+    """Data checks of stp_validate; raises StpError on failure (synchronises)."""
+    import torch
+    h = _h()
+    if stream is None:
+        stream = torch.cuda.current_stream(Q0.device)
+    h.check(h.lib.stp_validate(h.ptr, ctypes.c_void_p(stream.cuda_stream), degree, int(Q0.shape[0]),
+                               float(dt), _ptr(star), _ptr(E), _ptr(Q0)))
+
+
+def reference_matrices(degree: int):
+    """(Z [T,T], Sinv_w [T], Khat [3,B,B]) as the library computes them (host)."""
+    h = _h()
+    B, T = n_modes(degree), degree + 1
+    Z = np.zeros((T, T)); s = np.zeros(T); K = np.zeros((3, B, B))
+    h.check(h.lib.stp_reference_matrices(h.ptr, degree, Z.ctypes.data_as(ctypes.c_void_p),
+                                         s.ctypes.data_as(ctypes.c_void_p),
+                                         K.ctypes.data_as(ctypes.c_void_p)))
+    return Z, s, K
+
+
+def flops(degree: int):
+    """(paper upper bound of Algorithm 3, FLOP executed by the fused kernel) per element."""
+    lib = _lib.load()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    st = lib.stp_flops(degree, ctypes.byref(a), ctypes.byref(b))
+    if st != 0:
+        raise _lib.StpError(st)
+    return a.value, b.value

@@ -1,0 +1,71 @@
+// Compile-time sizes and temporal constants shared by the HIP kernels.
+//
+// Temporal basis chi_s(tau) = P_s(2 tau - 1) on [0, 1] (section "Space-Time
+// predictor" of Wolf et al., arXiv 2108.10565):
+//   S_rs = delta_rs / (2s+1),  W_rs = 1,  w_r = (-1)^r,
+//   K^tau_rs = 2 if r > s and r - s odd, else 0,
+// so Z = S^-1 (W - K^tau) (section "Block-wise back-substitution") has the
+// integer entries Z_us = (2u+1) * (u > s and u - s odd ? -1 : 1), and
+// (S^-1 w)_u = (2u+1) (-1)^u.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stp {
+
+constexpr int kNQ = 13;
+constexpr int kMaxDegree = 7;
+
+__host__ __device__ constexpr int n_modes(int N) { return (N + 1) * (N + 2) * (N + 3) / 6; }
+__host__ __device__ constexpr int block_size(int g) { return (g + 1) * (g + 2) / 2; }
+__host__ __device__ constexpr int block_start(int g) { return g * (g + 1) * (g + 2) / 6; }
+
+__host__ __device__ constexpr double z_entry(int u, int s) {
+  return (2.0 * u + 1.0) * ((u > s && ((u - s) & 1)) ? -1.0 : 1.0);
+}
+__host__ __device__ constexpr double sinv_w(int u) { return (2.0 * u + 1.0) * ((u & 1) ? -1.0 : 1.0); }
+
+// Launch arguments common to every kernel.  All pointers are device pointers.
+struct PredictArgs {
+  int64_t n;             // elements
+  double dt;
+  const double* star;    // [n][3][13][13]
+  const double* E;       // [n][13][13]
+  const double* Q0;      // [n][13][B]
+  double* Q;             // [n][13][B][T]
+  double* Qint;          // [n][13][B] or nullptr
+};
+
+// Launchers (one per kernel family); return hipSuccess or the launch error.
+hipError_t launch_reference_kernel(int N, const PredictArgs& a, hipStream_t stream);
+// The fused kernel is compiled once per degree (STP_DEGREE); each object
+// defines the specialisation for its degree.
+template <int N>
+hipError_t launch_fused_degree(const PredictArgs& a, int precision, int refine_steps, hipStream_t stream);
+template <> hipError_t launch_fused_degree<0>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<1>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<2>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<3>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<4>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<5>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<6>(const PredictArgs&, int, int, hipStream_t);
+template <> hipError_t launch_fused_degree<7>(const PredictArgs&, int, int, hipStream_t);
+
+inline hipError_t launch_fused_kernel(int N, const PredictArgs& a, int precision, int refine_steps,
+                                      hipStream_t stream) {
+  switch (N) {
+    case 0: return launch_fused_degree<0>(a, precision, refine_steps, stream);
+    case 1: return launch_fused_degree<1>(a, precision, refine_steps, stream);
+    case 2: return launch_fused_degree<2>(a, precision, refine_steps, stream);
+    case 3: return launch_fused_degree<3>(a, precision, refine_steps, stream);
+    case 4: return launch_fused_degree<4>(a, precision, refine_steps, stream);
+    case 5: return launch_fused_degree<5>(a, precision, refine_steps, stream);
+    case 6: return launch_fused_degree<6>(a, precision, refine_steps, stream);
+    case 7: return launch_fused_degree<7>(a, precision, refine_steps, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace stp

@@ -1,0 +1,208 @@
+// C ABI of the space-time predictor library (declared in include/stp.h).
+// Host-side argument checks, kernel dispatch, data validation, reference
+// matrices and FLOP counts.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/stp.h"
+#include "basis.hpp"
+#include "common.hpp"
+
+struct stp_handle_s {
+  std::string last_error;
+};
+
+namespace {
+
+stp_status fail(stp_handle h, stp_status s, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return s;
+}
+
+stp_status hip_fail(stp_handle h, hipError_t err, const char* where) {
+  return fail(h, STP_EHIP, std::string(where) + ": " + hipGetErrorString(err));
+}
+
+// Validation flags written by the validate kernel.
+constexpr int kFlagNonFinite = 1;
+constexpr int kFlagNotUpper = 2;
+constexpr int kFlagSingular = 4;
+
+__global__ void validate_kernel(int64_t n, int B, double dt, const double* star, const double* E,
+                                const double* Q0, int* flags) {
+  const int64_t per = 3 * 169 + 169 + 13 * static_cast<int64_t>(B);
+  int f = 0;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < n * per;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t e = t / per, r = t % per;
+    double v;
+    if (r < 3 * 169) {
+      v = star[e * 3 * 169 + r];
+    } else if (r < 4 * 169) {
+      const int k = static_cast<int>(r - 3 * 169), row = k / 13, col = k % 13;
+      v = E[e * 169 + k];
+      if (row > col && v != 0.0) f |= kFlagNotUpper;
+      if (row == col && dt * v >= 0.5) f |= kFlagSingular;
+    } else {
+      v = Q0[e * 13 * B + (r - 4 * 169)];
+    }
+    if (!std::isfinite(v)) f |= kFlagNonFinite;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+stp_status check_common(stp_handle h, int degree, int64_t n, double dt) {
+  if (!h) return STP_EINVAL;
+  if (degree < 0 || degree > STP_MAX_DEGREE)
+    return fail(h, STP_EDEGREE, "degree must be in 0..7, got " + std::to_string(degree));
+  if (n < 0) return fail(h, STP_EINVAL, "n_elements < 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, STP_EINVAL, "dt must be > 0 and finite");
+  return STP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stp_status stp_create(stp_handle* handle) {
+  if (!handle) return STP_EINVAL;
+  *handle = new (std::nothrow) stp_handle_s();
+  return *handle ? STP_OK : STP_ENOMEM;
+}
+
+stp_status stp_destroy(stp_handle handle) {
+  if (!handle) return STP_EINVAL;
+  delete handle;
+  return STP_OK;
+}
+
+stp_status stp_workspace_size(stp_handle handle, int degree, int64_t n_elements,
+                              stp_precision precision, int refine_steps, size_t* bytes) {
+  if (!handle || !bytes) return STP_EINVAL;
+  if (degree < 0 || degree > STP_MAX_DEGREE) return fail(handle, STP_EDEGREE, "degree out of range");
+  if (n_elements < 0) return fail(handle, STP_EINVAL, "n_elements < 0");
+  if (precision != STP_FP64 && precision != STP_FP32_REFINE) return fail(handle, STP_EINVAL, "precision");
+  if (refine_steps < 0 || refine_steps > STP_MAX_REFINE) return fail(handle, STP_EINVAL, "refine_steps");
+  *bytes = 0;
+  return STP_OK;
+}
+
+stp_status stp_predict(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
+                       const double* star, const double* E, const double* Q0, double* Q, double* Qint,
+                       stp_precision precision, int refine_steps, void* workspace,
+                       size_t workspace_bytes, unsigned flags) {
+  (void)workspace;
+  (void)workspace_bytes;
+  stp_status st = check_common(handle, degree, n_elements, dt);
+  if (st != STP_OK) return st;
+  handle->last_error.clear();
+  if (precision != STP_FP64 && precision != STP_FP32_REFINE)
+    return fail(handle, STP_EINVAL, "unknown precision");
+  if (refine_steps < 0 || refine_steps > STP_MAX_REFINE)
+    return fail(handle, STP_EINVAL, "refine_steps must be in 0..3");
+  if (flags & ~STP_FLAG_REFERENCE_KERNEL) return fail(handle, STP_EINVAL, "unknown flags");
+  if ((flags & STP_FLAG_REFERENCE_KERNEL) && precision != STP_FP64)
+    return fail(handle, STP_EINVAL, "the reference kernel is float64 only");
+  if (n_elements == 0) return STP_OK;
+  if (!star || !E || !Q0 || !Q) return fail(handle, STP_EINVAL, "NULL array pointer");
+  stp::PredictArgs a{n_elements, dt, star, E, Q0, Q, Qint};
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t err;
+  if (flags & STP_FLAG_REFERENCE_KERNEL)
+    err = stp::launch_reference_kernel(degree, a, stream);
+  else
+    err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps, stream);
+  if (err != hipSuccess) return hip_fail(handle, err, "kernel launch");
+  return STP_OK;
+}
+
+stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
+                        const double* star, const double* E, const double* Q0) {
+  stp_status st = check_common(handle, degree, n_elements, dt);
+  if (st != STP_OK) return st;
+  handle->last_error.clear();
+  if (n_elements == 0) return STP_OK;
+  if (!star || !E || !Q0) return fail(handle, STP_EINVAL, "NULL array pointer");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int* dflags = nullptr;
+  hipError_t err = hipMalloc(&dflags, sizeof(int));
+  if (err != hipSuccess) return hip_fail(handle, err, "hipMalloc");
+  int hflags = 0;
+  err = hipMemcpyAsync(dflags, &hflags, sizeof(int), hipMemcpyHostToDevice, stream);
+  if (err == hipSuccess) {
+    const int B = stp::n_modes(degree);
+    hipLaunchKernelGGL(validate_kernel, dim3(1024), dim3(256), 0, stream, n_elements, B, dt, star, E, Q0,
+                       dflags);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess) err = hipMemcpyAsync(&hflags, dflags, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  hipError_t ferr = hipFree(dflags);
+  if (err != hipSuccess) return hip_fail(handle, err, "validate");
+  if (ferr != hipSuccess) return hip_fail(handle, ferr, "hipFree");
+  if (hflags & kFlagNonFinite) return fail(handle, STP_ENONFINITE, "non-finite value in star, E or Q0");
+  if (hflags & kFlagNotUpper) return fail(handle, STP_ENOTUPPER, "E has a non-zero below its diagonal");
+  if (hflags & kFlagSingular) return fail(handle, STP_ESINGULAR, "dt * E_pp >= 0.5 for some quantity");
+  return STP_OK;
+}
+
+stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z, double* Sinv_w, double* Khat) {
+  if (!handle) return STP_EINVAL;
+  if (degree < 0 || degree > STP_MAX_DEGREE) return fail(handle, STP_EDEGREE, "degree out of range");
+  try {
+    const stp_host::ReferenceMatrices R = stp_host::build_reference_matrices(degree);
+    if (Z) std::memcpy(Z, R.Z.data(), R.Z.size() * sizeof(double));
+    if (Sinv_w) std::memcpy(Sinv_w, R.Sinv_w.data(), R.Sinv_w.size() * sizeof(double));
+    if (Khat) std::memcpy(Khat, R.Khat.data(), R.Khat.size() * sizeof(double));
+  } catch (const std::bad_alloc&) {
+    return fail(handle, STP_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(handle, STP_EINVAL, "reference matrices");
+  }
+  return STP_OK;
+}
+
+stp_status stp_flops(int degree, double* paper_bound, double* executed) {
+  if (degree < 0 || degree > STP_MAX_DEGREE) return STP_EDEGREE;
+  const double N = degree, B = stp::n_modes(degree), T = N + 1, Qn = 13;
+  if (paper_bound) {
+    // upper bound of Algorithm 3 (section "Block-wise back-substitution")
+    *paper_bound = 2 * B * (Qn * T * T + 3 * T + 3 * T * Qn * Qn + 3 * T * Qn * B) + 3 * Qn * B * T * T;
+  }
+  if (executed) {
+    // the fused float64 kernel: right-hand side init, dark-blue solves,
+    // three G couplings of the poroelastic E, dense star products of every
+    // mode above degree 0, non-zero Khat entries.
+    const stp_host::ReferenceMatrices R = stp_host::build_reference_matrices(degree);
+    double nnz = 0;
+    for (int d = 0; d < 3; ++d)
+      for (int g = 1; g <= degree; ++g)
+        for (int n = 0; n < stp::block_start(g); ++n)
+          for (int l = stp::block_start(g); l < stp::block_start(g) + stp::block_size(g); ++l)
+            nnz += (R.Khat[(static_cast<size_t>(d) * R.B + n) * R.B + l] != 0.0);
+    *executed = Qn * B * T + 2 * Qn * T * T * B + 3 * 2 * T * B + 2 * 3 * Qn * Qn * T * (B - 1) +
+                2 * Qn * T * nnz;
+  }
+  return STP_OK;
+}
+
+const char* stp_status_string(stp_status status) {
+  switch (status) {
+    case STP_OK: return "STP_OK";
+    case STP_EINVAL: return "STP_EINVAL: invalid argument";
+    case STP_EDEGREE: return "STP_EDEGREE: degree out of range";
+    case STP_ENOTUPPER: return "STP_ENOTUPPER: E is not upper triangular";
+    case STP_ESINGULAR: return "STP_ESINGULAR: diagonal block not safely invertible";
+    case STP_ENOMEM: return "STP_ENOMEM: out of memory";
+    case STP_EHIP: return "STP_EHIP: HIP runtime error";
+    case STP_EWORKSPACE: return "STP_EWORKSPACE: workspace too small";
+    case STP_ENONFINITE: return "STP_ENONFINITE: non-finite input";
+  }
+  return "unknown status";
+}
+
+const char* stp_last_error(stp_handle handle) { return handle ? handle->last_error.c_str() : ""; }
+
+}  // extern "C"

