@@ -1,0 +1,242 @@
+"""Benchmark of the element-local space-time predictor on one MI355X.
+
+One step = one predictor call over the whole batch of elements (all of
+Algorithm 3 for every element: setup, dark-blue solves, G coupling, star x
+stiffness x time updates, outputs).  Inputs are generated on the host from
+seeds, uploaded once, and are resident in HBM when the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  `value` is element-updates/s of the float64 path on
+the N=6 workload of 262,144 heterogeneous poroelastic elements; the float32
+chain + refinement path is timed on the same inputs and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2108_10565_amd import workload as wl  # noqa: E402
+
+PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(N: int, khat_nnz: int, star_nnz: int = 54, g_nnz: int = 3) -> int:
+    """FLOP per element that Algorithm 3 cannot avoid: RHS initialisation,
+    dark-blue T x T solves, G couplings, star products with the non-zeros of
+    the poroelastic star matrices (54 per direction) for every mode above
+    degree 0, and the non-zero Khat entries (the sparsity-aware count)."""
+    B, T = wl.n_modes(N), N + 1
+    return (13 * B * T + 2 * 13 * T * T * B + 2 * T * B * g_nnz + 2 * 3 * star_nnz * T * (B - 1)
+            + 2 * 13 * T * khat_nnz)
+
+
+def dense_block_flops(N: int) -> int:
+    """Same count with dense star matrices and dense Khat upper blocks."""
+    B, T = wl.n_modes(N), N + 1
+    up = sum(g * (g + 1) * (g + 2) // 6 * (g + 1) * (g + 2) // 2 for g in range(1, N + 1))
+    return (13 * B * T + 2 * 13 * T * T * B + 2 * T * B * 3 + 2 * 3 * 169 * T * (B - 1)
+            + 2 * 13 * T * 3 * up)
+
+
+def hbm_bytes(N: int) -> int:
+    """Compulsory HBM bytes per element of one float64 call: read Q0, star, E;
+    write Q and Qint."""
+    B, T = wl.n_modes(N), N + 1
+    return 8 * (13 * B + 3 * 169 + 169 + 13 * B * T + 13 * B)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, one element per core, before the GPU is touched
+# ---------------------------------------------------------------------------
+
+def _oracle_one(args):
+    N, star, E, Q0, dt = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        from oracle import stp as ostp
+        t = time.perf_counter()
+        X, Qi = ostp.solve_element(N, star, E, Q0, dt)
+        return X, Qi, time.perf_counter() - t
+
+
+def cpu_baseline(w, ids, procs):
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    jobs = [(w.N, w.star[i], w.E[i], w.Q0[i], w.dt) for i in ids]
+    t = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_one, jobs)
+    wall = time.perf_counter() - t
+    return res, wall
+
+
+# ---------------------------------------------------------------------------
+
+def time_path(torch, api, dev, w, steps, warmup, **kw):
+    """Warm up, then time `steps` calls with HIP events on torch's current
+    stream (the stream the library launches on)."""
+    Q = torch.empty((w.n, 13, wl.n_modes(w.N), w.N + 1), dtype=torch.float64, device="cuda")
+    Qi = torch.empty((w.n, 13, wl.n_modes(w.N)), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        api.predict(dev["Q0"], dev["star"], dev["E"], w.dt, w.N, Q=Q, Qint=Qi, **kw)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_start.record()
+    for k in range(steps):
+        ev[k][0].record()
+        api.predict(dev["Q0"], dev["star"], dev["E"], w.dt, w.N, Q=Q, Qint=Qi, **kw)
+        ev[k][1].record()
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_call = [a.elapsed_time(b) for a, b in ev]
+    total_ms = t_start.elapsed_time(t_end)
+    return dict(ms_per_step=total_ms / steps, call_ms_mean=float(np.mean(per_call)),
+                call_ms_median=float(np.median(per_call)), call_ms_min=float(np.min(per_call)),
+                wall_s=wall), Q, Qi
+
+
+def rel_l2(X, Xo):
+    ax = tuple(range(1, X.ndim))
+    return np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n6_heterogeneous_262144")
+    ap.add_argument("--refine-steps", type=int, default=1)
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the predictor is element-local and this build runs on a "
+              f"single MI355X; --gpus {args.gpus} is not supported (shard elements across GPUs "
+              f"instead, see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    log(f"[bench] generating workload {args.workload}")
+    t = time.perf_counter()
+    w = wl.make_workload(args.workload)
+    log(f"[bench] generated n={w.n} N={w.N} dt={w.dt:.4e} in {time.perf_counter() - t:.1f}s")
+    sample = wl.oracle_sample(w.n)
+
+    cpu = None
+    oracle = {}
+    if not args.no_cpu_baseline:
+        ncores = len(os.sched_getaffinity(0))
+        procs = args.cpu_procs or max(1, min(16, ncores))
+        ids = sample[:procs] if len(sample) >= procs else sample
+        log(f"[bench] cpu baseline: oracle on {len(ids)} elements, {procs} processes x 1 BLAS thread")
+        res, wall = cpu_baseline(w, ids, procs)
+        for i, (X, Qi, _) in zip(ids, res):
+            oracle[i] = (X, Qi)
+        cpu = {"value": len(ids) / wall, "unit": "element updates/s", "cores": min(procs, len(ids)),
+               "kind": "oracle",
+               "sample": f"{len(ids)} elements of {w.name} (ids {ids[:4]}...), dense LU + "
+                         f"extended-precision refinement, one element per process, 1 BLAS thread "
+                         f"each, wall {wall:.1f}s",
+               "per_element_s_mean": float(np.mean([r[2] for r in res]))}
+        log(f"[bench] cpu baseline {cpu['value']:.3f} el/s over {wall:.1f}s")
+
+    import torch
+    from paper_2108_10565_amd import api
+    log(f"[bench] device {torch.cuda.get_device_name(0)}")
+    dev = {k: torch.from_numpy(getattr(w, k)).to("cuda") for k in ("Q0", "star", "E")}
+    torch.cuda.synchronize()
+
+    _, _, Kh = api.reference_matrices(w.N)
+    nnz = sum(int((Kh[:, :wl.n_modes(g - 1), wl.n_modes(g - 1):wl.n_modes(g)] != 0).sum())
+              for g in range(1, w.N + 1))
+    F_alg = algorithmic_flops(w.N, nnz)
+    F_dense = dense_block_flops(w.N)
+    F_paper, F_exec = api.flops(w.N)
+    bytes_el = hbm_bytes(w.N)
+
+    paths = {}
+    log("[bench] fp64 path")
+    t64, Q, Qi = time_path(torch, api, dev, w, args.steps, args.warmup, precision="fp64")
+    err64 = None
+    if oracle:
+        ids = list(oracle)
+        Qs = Q[ids].cpu().numpy()
+        err64 = float(rel_l2(Qs, np.stack([oracle[i][0] for i in ids])).max())
+    paths["fp64"] = dict(t64, el_per_s=w.n / (t64["ms_per_step"] * 1e-3), max_rel_l2=err64)
+    log(f"[bench] fp64 {paths['fp64']['el_per_s'] / 1e6:.3f} M el/s, call {t64['call_ms_mean']:.3f} ms,"
+        f" max rel L2 {err64}")
+    del Q, Qi
+    torch.cuda.empty_cache()
+    if not args.skip_fp32:
+        try:
+            log(f"[bench] fp32 + {args.refine_steps} refinement step(s) path")
+            t32, Q, Qi = time_path(torch, api, dev, w, args.steps, args.warmup, precision="fp32_refine",
+                                   refine_steps=args.refine_steps)
+            err32 = None
+            if oracle:
+                ids = list(oracle)
+                err32 = float(rel_l2(Q[ids].cpu().numpy(), np.stack([oracle[i][0] for i in ids])).max())
+            paths["fp32_refine"] = dict(t32, refine_steps=args.refine_steps,
+                                        el_per_s=w.n / (t32["ms_per_step"] * 1e-3), max_rel_l2=err32)
+            log(f"[bench] fp32+refine {paths['fp32_refine']['el_per_s'] / 1e6:.3f} M el/s, max rel L2 {err32}")
+            del Q, Qi
+        except Exception as exc:  # reported, never silently replaced
+            paths["fp32_refine"] = dict(error=str(exc))
+            log(f"[bench] fp32+refine failed: {exc}")
+
+    p = paths["fp64"]
+    kernel_s = p["call_ms_mean"] * 1e-3
+    achieved = F_alg * w.n / kernel_s / 1e12
+    out = {
+        "metric": "element predictor updates/s at N=6 (FP64 vs FP32+refine @ rel L2<=1e-10), % roofline",
+        "value": p["el_per_s"],
+        "unit": "element updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": p["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded heterogeneous poroelastic materials, random tetrahedra, Q0 ~ N(0,1))",
+        "config": {"workload": w.name, "degree": w.N, "elements": w.n,
+                   "unknowns_per_element": 13 * wl.n_modes(w.N) * (w.N + 1), "dt": w.dt},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                     "flop_per_element": F_alg,
+                     "hbm_gbs": bytes_el * w.n / kernel_s / 1e9,
+                     "hbm_frac": bytes_el * w.n / kernel_s / 1e9 / PEAK_HBM_GBS,
+                     "bytes_per_element": bytes_el},
+        "cpu_baseline": cpu,
+        "paths": paths,
+        "flop_counts_per_element": {"algorithmic_sparse": F_alg, "dense_block": F_dense,
+                                    "executed_fused_kernel": F_exec, "paper_upper_bound": F_paper},
+    }
+    if "fp32_refine" in paths and "el_per_s" in paths["fp32_refine"]:
+        out["fp32_refine_value"] = paths["fp32_refine"]["el_per_s"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -13,19 +13,21 @@
 // scalar loads from a device table), exactly the zeros the Lemma of section
 // "Structure of the system matrix" and the Dubiner structure provide.
 //
-// Per chunk of kChunk modes m of degree block g (g = N .. 0):
+// Per chunk of up to kChunkMax modes m of degree block g (g = N .. 0):
 //   1. every lane writes b[m] to LDS (top block: b = Q0 (S^-1 w), eq:b_pmu);
-//   2. dark-blue blocks: lane (e, p, s) forms X[p, m, s] = row s of
-//      (Z - E*_pp I)^-1 times b[p, m, :] (float64, Zinv row in registers);
-//   3. G coupling in dependency levels: a quantity o whose row of the strict
-//      upper part G of E* is non-empty recomputes
-//      X[o] = (Z - E*_oo I)^-1 (b[o] + sum_p G_op X[p]) once every X[p] it
-//      depends on is final (level = longest chain below it); for the
-//      poroelastic E this is one extra round for u, v, w;
-//   4. green blocks: every lane reads X[q, m, u] of the 13 quantities, forms
-//      y_1..y_3 with its row of A^{1*}, A^{2*}, A^{3*}, and subtracts
-//      Khat^j[n, m] y_j from its registers b[n]; the chunk of X is written to
-//      Q (and dt X[:, :, 0] to Qint) with coalesced stores.
+//   2. dark-blue blocks and G coupling: lane (e, p, s) forms X[p, m, s] =
+//      row s of (Z - E*_pp I)^-1 times b[p, m, :] (float64).  A quantity o
+//      whose row of the strict upper part G of E* holds one coupling G_op to
+//      an uncoupled quantity p (the poroelastic u <- uf, v <- vf, w <- wf)
+//      uses the closed form X_o = Zinv_o (b_o + G_op X_p)
+//      = zr . b_o + dr . b_p with dr = G_op (row of Zinv_o) Zinv_p, so no
+//      extra round is needed; any other upper-triangular E is handled level
+//      by level (level = longest coupling chain below a quantity);
+//   3. green blocks: every lane reads X[q, m, u] of the quantities in its
+//      star row, forms y_1..y_3 with its row of A^{1*}, A^{2*}, A^{3*}, and
+//      subtracts Khat^j[n, m] y_j from its registers b[n];
+//   4. the chunk of X is written to Q (and dt X[:, :, 0] to Qint) with
+//      coalesced stores.
 // A^{j*} = dt A^j and E* = dt E are formed in-kernel, so every product runs
 // with unit scaling (the paper's libxsmm alpha = 1 remark, section "Roofline
 // model").
@@ -43,12 +45,12 @@ namespace {
 
 constexpr int kMaxThreads = 512;
 constexpr int kMaxElems = 16;
-constexpr int kChunk = 4;
+constexpr int kChunkMax = 10;  // modes per chunk (degree blocks are split evenly)
 // Non-zero columns kept per lane of a star-matrix row (union over the three
 // directions).  The poroelastic Jacobians need at most 6 (normal-stress and
 // pressure rows couple to the 6 velocities; velocity rows to 3 stresses and
 // the pressure); a workgroup holding any row with more falls back to reading
-// the dense rows from LDS.
+// the dense rows from global memory.
 constexpr int kStarNnz = 6;
 
 template <int I>
@@ -69,13 +71,48 @@ template <int N>
 struct Cfg {
   static constexpr int B = n_modes(N);
   static constexpr int T = N + 1;
-  static constexpr int TP = (T + 1) & ~1;          // time dimension padded for 16-byte LDS rows
-  static constexpr int LN = block_start(N);        // register-resident rows
+  static constexpr int LN = block_start(N);        // register-resident rows (below the top block)
   static constexpr int LR = LN > 0 ? LN : 1;
+  static constexpr int DN = block_size(N);         // modes of the top block (largest block)
   static constexpr int kCols = kNQ * T;            // lanes per element
   static constexpr int kElems =                    // elements per workgroup
       (kMaxThreads / kCols) < kMaxElems ? (kMaxThreads / kCols) : kMaxElems;
   static constexpr int kThreads = (kElems * kCols + 63) / 64 * 64;
+  static constexpr int kSlots = kElems + 1;        // + one dummy slot for spare lanes
+  static constexpr int kChunk = kChunkMax < DN ? kChunkMax : DN;
+  // Stride (doubles) of one (element, quantity) block of the chunk buffers,
+  // padded so that S = T (mod 16): the LDS address of lane (e, p, u) is then
+  // congruent to its lane index modulo 16 doubles (32 banks of 4 bytes), so
+  // the column-wise accesses of 16 consecutive lanes hit distinct banks.
+  static constexpr int kChunkT = kChunk * T;
+  static constexpr int S = kChunkT + (((T - kChunkT) % 16) + 16) % 16;
+};
+
+// Degree block g is processed in nchunks(g) chunks of near-equal size.
+__host__ __device__ constexpr int nchunks(int g, int cmax) { return (block_size(g) + cmax - 1) / cmax; }
+__host__ __device__ constexpr int chunk_size(int g, int cmax, int i) {
+  return block_size(g) / nchunks(g, cmax) + (i < block_size(g) % nchunks(g, cmax) ? 1 : 0);
+}
+__host__ __device__ constexpr int chunk_start(int g, int cmax, int i) {
+  return block_start(g) + i * (block_size(g) / nchunks(g, cmax)) +
+         (i < block_size(g) % nchunks(g, cmax) ? i : block_size(g) % nchunks(g, cmax));
+}
+
+template <int N, typename R>
+struct Shared {
+  using C = Cfg<N>;
+  double G[C::kSlots][kNQ][kNQ];            // E* (lower part zeroed)
+  double zr[C::kThreads][C::T];             // per lane (e, p, u): row u of (Z - E*_pp I)^-1
+  double dr[C::kThreads][C::T];             // per lane: row of Zinv_o G_op Zinv_p (closure coupling)
+  int level[C::kSlots][kNQ];
+  int maxlevel;
+  union {
+    double A[C::kSlots][3][kNQ][kNQ];       // setup only: A^{j*} = dt A^j
+    struct {
+      R bufB[C::kSlots * kNQ * C::S];       // b of the chunk: [e][p] blocks of [chunk][T], stride S
+      R bufX[C::kSlots * kNQ * C::S];       // X of the chunk, same layout
+    } c;
+  } u;
 };
 
 // The usage-ordered Khat table of degree N.  Kernels pass its address through
@@ -93,29 +130,18 @@ __device__ __forceinline__ const double* khat_sparse() {
   else return stp_gen::kKhatSparse7;
 }
 
-template <int N, typename R>
-struct Shared {
-  using C = Cfg<N>;
-  double q0[C::kElems][kNQ][C::B];          // initial spatial DOFs of the group
-  double A[C::kElems][3][kNQ][kNQ];         // A^{j*} = dt A^j of the group
-  double G[C::kElems][kNQ][kNQ];            // E* (lower part zeroed)
-  R bufB[C::kElems][kNQ][kChunk][C::TP];    // b of the chunk
-  R bufX[C::kElems][kNQ][kChunk][C::TP];    // X of the chunk
-  int level[C::kElems][kNQ];
-  int maxlevel;
-};
-
-// Row s of (Z - z I)^-1: solves (Z - z I)^T y = e_s by Gauss-Jordan
-// elimination without pivoting (eigenvalues of Z have real part >= 1, so for
-// z <= 0.5 the pivots stay away from zero; accurate to ~1e-15 there).
+// Solves (Z - z I)^T y = rhs by Gauss-Jordan elimination without pivoting
+// (the eigenvalues of Z have real part >= 1, so for z <= 0.5 the pivots stay
+// away from zero; accurate to ~1e-15 there).  With rhs = e_s, y is row s of
+// (Z - z I)^-1.
 template <int T>
-__device__ __forceinline__ void zinv_row(double z, int s, double (&out)[T]) {
+__device__ __forceinline__ void zt_solve(double z, const double (&rhs)[T], double (&out)[T]) {
   double a[T][T + 1];
 #pragma unroll
   for (int r = 0; r < T; ++r) {
 #pragma unroll
     for (int c = 0; c < T; ++c) a[r][c] = z_entry(c, r) - (r == c ? z : 0.0);  // transpose
-    a[r][T] = (r == s) ? 1.0 : 0.0;
+    a[r][T] = rhs[r];
   }
 #pragma unroll
   for (int k = 0; k < T; ++k) {
@@ -153,6 +179,26 @@ __device__ __forceinline__ void load_group(const double* kv, double (&v)[kGroup]
   const ConstDouble* kc = (const ConstDouble*)kp;
 #pragma unroll
   for (int i = 0; i < gn; ++i) v[i] = kc[i];
+}
+
+// Brings the Khat coefficients of columns [M0, M0 + CNT) into the scalar
+// data cache: every wave of the workgroup loads one dword of every
+// nwaves-th 64-byte line of the range and waits for it.  Issued before the
+// chunk's first barrier, so the latency overlaps the other waves' work and
+// the later per-group loads of the green update hit the cache.
+template <int N, int M0, int CNT>
+__device__ __forceinline__ void prefetch_columns(const double* kv, int wave, int nwaves) {
+  using P = stp_gen::KhatPattern<N>;
+  constexpr int first = P::col_start[M0];
+  constexpr int last = P::col_start[M0 + CNT - 1] + P::col_count[M0 + CNT - 1];
+  if constexpr (last > first) {
+    constexpr int line0 = first / 8, line1 = (last + 7) / 8;  // 8 doubles per line (64-byte aligned table)
+    for (int line = line0 + wave; line < line1; line += nwaves) {
+      const double* kp = kv + line * 8;
+      asm volatile("" : "+s"(kp));
+      use_s(*(const ConstDouble*)kp);
+    }
+  }
 }
 
 // b[n] -= Khat^j[n, M] y_j for the non-zeros of column M (usage order of the
@@ -205,41 +251,41 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
   using R = double;
   constexpr int B = C::B, T = C::T, kE = C::kElems, kThreads = C::kThreads;
   __shared__ Shared<N, R> sh;
+  R* const bufB = sh.u.c.bufB;
+  R* const bufX = sh.u.c.bufX;
   const int tid = threadIdx.x;
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
   const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
   const int nloc = static_cast<int>(nloc64);
-  int es = tid / C::kCols;
+  // spare lanes past kElems * kCols share the dummy slot kElems (their
+  // values are never stored to memory)
+  const int es = (tid / C::kCols) < kE ? (tid / C::kCols) : kE;
   const int col = tid % C::kCols;
   const int p = col / T, u = col % T;
   const bool active = es < nloc;
-  // spare lanes past kElems * kCols alias the last slot for their reads only;
-  // they never write LDS or memory
-  const bool spare = es >= kE;
-  if (spare) es = kE - 1;
+  const int cb = (es * kNQ + p) * C::S;  // this lane's (element, quantity) block in bufB / bufX
   const double* kv = khat_sparse<N>();
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
 
-  // ---- stage Q0 and E* of the group (coalesced)
-  {
-    const double* src = a.Q0 + e0 * (kNQ * B);
-    double* dst = &sh.q0[0][0][0];
-    for (int i = tid; i < nloc * kNQ * B; i += kThreads) dst[i] = src[i];
-    const double* Esrc = a.E + e0 * (kNQ * kNQ);
-    double* Gd = &sh.G[0][0][0];
-    for (int i = tid; i < kE * kNQ * kNQ; i += kThreads) {
-      const int r = (i / kNQ) % kNQ, c = i % kNQ;
-      Gd[i] = (i < nloc * kNQ * kNQ && c >= r) ? a.dt * Esrc[i] : 0.0;
-    }
-    if (tid == 0) sh.maxlevel = 0;
+  // ---- stage E* and A^{j*} of the group (coalesced)
+  for (int i = tid; i < C::kSlots * kNQ * kNQ; i += kThreads) {
+    const int r = (i / kNQ) % kNQ, c = i % kNQ;
+    (&sh.G[0][0][0])[i] = (i < nloc * kNQ * kNQ && c >= r) ? a.dt * a.E[e0 * (kNQ * kNQ) + i] : 0.0;
   }
+  for (int i = tid; i < C::kSlots * 3 * kNQ * kNQ; i += kThreads)
+    (&sh.u.A[0][0][0][0])[i] = i < nloc * 3 * kNQ * kNQ ? a.dt * a.star[e0 * (3 * kNQ * kNQ) + i] : 0.0;
+  if (tid == 0) sh.maxlevel = 0;
+  // register rows of b: b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
+  R b[C::LR];
   {
-    const double* Asrc = a.star + e0 * (3 * kNQ * kNQ);
-    double* Ad = &sh.A[0][0][0][0];
-    for (int i = tid; i < nloc * 3 * kNQ * kNQ; i += kThreads) Ad[i] = a.dt * Asrc[i];
-    for (int i = nloc * 3 * kNQ * kNQ + tid; i < kE * 3 * kNQ * kNQ; i += kThreads) Ad[i] = 0.0;
+    const double w = sinv_w(u);
+    const double* q0row = a.Q0 + ((active ? e0 + es : 0) * kNQ + p) * B;
+#pragma unroll
+    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w);
   }
   __syncthreads();
-  // dependency levels of the strict upper part of E*, one thread per element
+
+  // ---- dependency levels of the strict upper part of E*, one thread per element
   if (tid < nloc) {
     int lev[kNQ];
     int mx = 0;
@@ -255,10 +301,17 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
     }
     atomicMax(&sh.maxlevel, mx);
   }
+  // ---- row u of (Z - E*_pp I)^-1 (kept in LDS, loaded for the dark-blue step)
   double zr[T];
-  zinv_row<T>(sh.G[es][p][p], u, zr);
-  // sparse row p of the three star matrices: columns sq[k] (as LDS offsets
-  // into the chunk buffer) and coefficients sa0..sa2[k]
+  {
+    double e_u[T];
+#pragma unroll
+    for (int v = 0; v < T; ++v) e_u[v] = (v == u) ? 1.0 : 0.0;
+    zt_solve<T>(sh.G[es][p][p], e_u, zr);
+#pragma unroll
+    for (int v = 0; v < T; ++v) sh.zr[tid][v] = zr[v];
+  }
+  // ---- sparse row p of the three star matrices
   double sa0[kStarNnz], sa1[kStarNnz], sa2[kStarNnz];
   int sq[kStarNnz];
   bool overflow = false;
@@ -267,11 +320,11 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
 #pragma unroll
     for (int k = 0; k < kStarNnz; ++k) {
       sa0[k] = sa1[k] = sa2[k] = 0.0;
-      sq[k] = 0;
+      sq[k] = cb + u;
     }
 #pragma unroll
     for (int q = 0; q < kNQ; ++q) {
-      const double v0 = sh.A[es][0][p][q], v1 = sh.A[es][1][p][q], v2 = sh.A[es][2][p][q];
+      const double v0 = sh.u.A[es][0][p][q], v1 = sh.u.A[es][1][p][q], v2 = sh.u.A[es][2][p][q];
       if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
 #pragma unroll
         for (int k = 0; k < kStarNnz; ++k)
@@ -279,79 +332,138 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
             sa0[k] = v0;
             sa1[k] = v1;
             sa2[k] = v2;
-            sq[k] = q * kChunk * C::TP;
+            sq[k] = (es * kNQ + q) * C::S + u;
           }
         ++cnt;
       }
     }
     overflow = active && cnt > kStarNnz;
   }
-  R b[C::LR];
-  {
-    const double w = sinv_w(u);
-#pragma unroll
-    for (int n = 0; n < C::LN; ++n) b[n] = sh.q0[es][p][n] * w;
+  // ---- G coupling of this lane's quantity
+  int gcount = 0, gp = p;
+  double gcoef = 0.0;
+  for (int q = p + 1; q < kNQ; ++q) {
+    const double gq = sh.G[es][p][q];
+    if (gq != 0.0) {
+      if (gcount == 0) {
+        gcoef = gq;
+        gp = q;
+      }
+      ++gcount;
+    }
   }
-  const bool dense_star = __syncthreads_or(overflow);
-  const int mylevel = active ? sh.level[es][p] : 0;
+  // uniform over the workgroup: scalar branches, no exec masking.  This
+  // barrier also orders the setup's reads of A before the chunk buffers
+  // (which share its storage) are written.
+  const bool dense_star = __builtin_amdgcn_readfirstlane(__syncthreads_or(overflow)) != 0;
   const int maxlevel = sh.maxlevel;
+  const int mylevel = active ? sh.level[es][p] : 0;
+  const int gp_level = active ? sh.level[es][gp] : 0;
+  // closure form of the coupling when every coupled quantity couples to one
+  // quantity that itself is uncoupled (the poroelastic case):
+  //   X_o = Zinv_o (b_o + g X_p) = zr . b_o + dr . b_p,
+  //   dr = g * (row of Zinv_o) * Zinv_p, i.e. (Z - E*_pp I)^T dr = g zr
+  const bool closure = __builtin_amdgcn_readfirstlane(
+                           __syncthreads_and(!active || (gcount <= 1 && (gcount == 0 || gp_level == 0)))) != 0;
+  const int pb = (es * kNQ + gp) * C::S;  // block of the coupled quantity (own block if uncoupled)
+  {
+    double dr[T];
+    if (gcount == 1 && closure) {
+      double rhs[T];
+#pragma unroll
+      for (int v = 0; v < T; ++v) rhs[v] = gcoef * zr[v];
+      zt_solve<T>(sh.G[es][gp][gp], rhs, dr);
+    } else {
+#pragma unroll
+      for (int v = 0; v < T; ++v) dr[v] = 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < T; ++v) sh.dr[tid][v] = dr[v];
+  }
 
   static_for<0, N + 1>([&](auto gi) __attribute__((always_inline)) {
     constexpr int g = N - decltype(gi)::value;
-    constexpr int L0 = block_start(g), D = block_size(g);
-    constexpr int nchunks = (D + kChunk - 1) / kChunk;
-    static_for<0, nchunks>([&](auto ci) __attribute__((always_inline)) {
-      constexpr int m0 = L0 + decltype(ci)::value * kChunk;
-      constexpr int c = (D - decltype(ci)::value * kChunk) < kChunk ? (D - decltype(ci)::value * kChunk) : kChunk;
-      // 1. right-hand side of the chunk to LDS
-      static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-        constexpr int m = m0 + decltype(k)::value;
-        R v;
-        if constexpr (g == N) v = sh.q0[es][p][m] * sinv_w(u);
-        else v = b[m];
-        if (!spare) sh.bufB[es][p][decltype(k)::value][u] = v;
-      });
-      __syncthreads();
-      // 2. dark-blue solves: X[p, m, u] = sum_v Zinv_p[u][v] b[p, m, v]
-      static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-        double x = 0.0;
-#pragma unroll
-        for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(sh.bufB[es][p][decltype(k)::value][v]), x);
-        if (!spare) sh.bufX[es][p][decltype(k)::value][u] = static_cast<R>(x);
-      });
-      __syncthreads();
-      // 3. G coupling, level by level
-      for (int r = 1; r <= maxlevel; ++r) {
-        if (mylevel == r && !spare) {
-          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-            constexpr int kk = decltype(k)::value;
-            double acc[T];
-#pragma unroll
-            for (int v = 0; v < T; ++v) acc[v] = static_cast<double>(sh.bufB[es][p][kk][v]);
-            for (int q = p + 1; q < kNQ; ++q) {
-              const double gq = sh.G[es][p][q];
-              if (gq != 0.0) {
-#pragma unroll
-                for (int v = 0; v < T; ++v) acc[v] = fma(gq, static_cast<double>(sh.bufX[es][q][kk][v]), acc[v]);
-              }
-            }
-            double x = 0.0;
-#pragma unroll
-            for (int v = 0; v < T; ++v) x = fma(zr[v], acc[v], x);
-            sh.bufX[es][p][kk][u] = static_cast<R>(x);
-          });
+    static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
+      constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
+      constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
+      if constexpr (g > 0) prefetch_columns<N, m0, c>(kv, wave, kThreads / 64);
+      // 1. right-hand side of the chunk to LDS; the top block has received
+      //    no update yet: b = Q0 (S^-1 w), copied straight from memory
+      if constexpr (g == N) {
+        for (int i = tid; i < nloc * kNQ * c * T; i += kThreads) {
+          const int ee = i / (kNQ * c * T), r = i % (kNQ * c * T);
+          const int pp = r / (c * T), kk = (r / T) % c, uu = r % T;
+          bufB[(ee * kNQ + pp) * C::S + kk * T + uu] =
+              static_cast<R>(a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] * sinv_w(uu));
         }
-        __syncthreads();
+      } else {
+        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+          bufB[cb + decltype(k)::value * T + u] = b[m0 + decltype(k)::value];
+        });
       }
-      // 4. green blocks (lane-local) and output of the chunk
+      __syncthreads();
+      // 2. dark-blue blocks and G coupling
+      double zr[T];
+#pragma unroll
+      for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
+      if (closure) {
+        double drr[T];
+#pragma unroll
+        for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
+        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+          constexpr int kk = decltype(k)::value;
+          double x = 0.0;
+#pragma unroll
+          for (int v = 0; v < T; ++v) {
+            x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+            x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
+          }
+          bufX[cb + kk * T + u] = static_cast<R>(x);
+        });
+      } else {
+        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+          constexpr int kk = decltype(k)::value;
+          double x = 0.0;
+#pragma unroll
+          for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+          bufX[cb + kk * T + u] = static_cast<R>(x);
+        });
+        // general upper-triangular E: level by level, each level after the
+        // levels it depends on
+        for (int r = 1; r <= maxlevel; ++r) {
+          __syncthreads();
+          if (mylevel == r) {
+            static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+              constexpr int kk = decltype(k)::value;
+              double acc[T];
+#pragma unroll
+              for (int v = 0; v < T; ++v) acc[v] = static_cast<double>(bufB[cb + kk * T + v]);
+              for (int q = p + 1; q < kNQ; ++q) {
+                const double gq = sh.G[es][p][q];
+                if (gq != 0.0) {
+                  const int qb = (es * kNQ + q) * C::S + kk * T;
+#pragma unroll
+                  for (int v = 0; v < T; ++v) acc[v] = fma(gq, static_cast<double>(bufX[qb + v]), acc[v]);
+                }
+              }
+              double x = 0.0;
+#pragma unroll
+              for (int v = 0; v < T; ++v) x = fma(zr[v], acc[v], x);
+              bufX[cb + kk * T + u] = static_cast<R>(x);
+            });
+          }
+        }
+      }
+      __syncthreads();
+      // 3. green blocks (lane-local): star product, then Khat columns
       if constexpr (g > 0) {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
           R y0 = 0, y1 = 0, y2 = 0;
           // opaque per-mode offset: this mode's LDS reads stay here
-          int xoff = ((es * kNQ) * kChunk + kk) * C::TP + u;
+          int xoff = kk * T;
           asm volatile("" : "+v"(xoff));
-          const R* xs = &sh.bufX[0][0][0][0] + xoff;
+          const R* xs = bufX + xoff;
           if (!dense_star) {
 #pragma unroll
             for (int k = 0; k < kStarNnz; ++k) {
@@ -361,12 +473,13 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
               y2 = fma(static_cast<R>(sa2[k]), xq, y2);
             }
           } else {
+            const double* st = a.star + (active ? e0 + es : 0) * (3 * kNQ * kNQ) + p * kNQ;
 #pragma unroll
             for (int q = 0; q < kNQ; ++q) {
-              const R xq = xs[q * kChunk * C::TP];
-              y0 = fma(static_cast<R>(sh.A[es][0][p][q]), xq, y0);
-              y1 = fma(static_cast<R>(sh.A[es][1][p][q]), xq, y1);
-              y2 = fma(static_cast<R>(sh.A[es][2][p][q]), xq, y2);
+              const R xq = xs[(es * kNQ + q) * C::S + u];
+              y0 = fma(static_cast<R>(a.dt * st[q]), xq, y0);
+              y1 = fma(static_cast<R>(a.dt * st[kNQ * kNQ + q]), xq, y1);
+              y2 = fma(static_cast<R>(a.dt * st[2 * kNQ * kNQ + q]), xq, y2);
             }
           }
           green_column<N, m0 + kk, R>(b, y0, y1, y2, kv);
@@ -374,20 +487,21 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
           __builtin_amdgcn_sched_barrier(0);
         });
       }
+      // 4. the chunk's space-time DOFs to memory (coalesced runs of c*T)
       {
         double* Qg = a.Q + e0 * (kNQ * B * T);
         constexpr int per = c * T;
         for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
           const int ee = i / (kNQ * per), rem = i % (kNQ * per);
           const int pp = rem / per, r = rem % per;
-          Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r] = sh.bufX[ee][pp][r / T][r % T];
+          Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r] = bufX[(ee * kNQ + pp) * C::S + r];
         }
         if (a.Qint) {
           double* Ig = a.Qint + e0 * (kNQ * B);
           for (int i = tid; i < nloc * kNQ * c; i += kThreads) {
             const int ee = i / (kNQ * c), rem = i % (kNQ * c);
             const int pp = rem / c, kk = rem % c;
-            Ig[(ee * kNQ + pp) * B + m0 + kk] = a.dt * sh.bufX[ee][pp][kk][0];
+            Ig[(ee * kNQ + pp) * B + m0 + kk] = a.dt * bufX[(ee * kNQ + pp) * C::S + kk * T];
           }
         }
       }
