@@ -26,8 +26,8 @@
 //   3. green blocks: every lane reads X[q, m, u] of the quantities in its
 //      star row, forms y_1..y_3 with its row of A^{1*}, A^{2*}, A^{3*}, and
 //      subtracts Khat^j[n, m] y_j from its registers b[n];
-//   4. the chunk of X is written to Q (and dt X[:, :, 0] to Qint) with
-//      coalesced stores.
+//   X of the chunk goes to Q (and dt X[:, :, 0] to Qint) from step 2 (or
+//   after the last level for a general E).
 // A^{j*} = dt A^j and E* = dt E are formed in-kernel, so every product runs
 // with unit scaling (the paper's libxsmm alpha = 1 remark, section "Roofline
 // model").
@@ -56,6 +56,7 @@ constexpr int kStarNnz = 6;
 template <int I>
 using ic = std::integral_constant<int, I>;
 using ConstDouble = __attribute__((address_space(4))) const double;
+using ConstUint = __attribute__((address_space(4))) const unsigned;
 
 template <int Begin, class F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
@@ -182,22 +183,27 @@ __device__ __forceinline__ void load_group(const double* kv, double (&v)[kGroup]
 }
 
 // Brings the Khat coefficients of columns [M0, M0 + CNT) into the scalar
-// data cache: every wave of the workgroup loads one dword of every
-// nwaves-th 64-byte line of the range and waits for it.  Issued before the
-// chunk's first barrier, so the latency overlaps the other waves' work and
-// the later per-group loads of the green update hit the cache.
-template <int N, int M0, int CNT>
-__device__ __forceinline__ void prefetch_columns(const double* kv, int wave, int nwaves) {
+// data cache: wave w loads one dword of each line w, w + nwaves, ... of the
+// range (64-byte lines, table 64-byte aligned), issuing every load before
+// waiting once, so the line fetches overlap each other and the other waves'
+// work; the per-group loads of the green update then hit the cache.
+template <int N, int M0, int CNT, int NWAVES>
+__device__ __forceinline__ void prefetch_columns(const double* kv, int wave) {
   using P = stp_gen::KhatPattern<N>;
   constexpr int first = P::col_start[M0];
   constexpr int last = P::col_start[M0 + CNT - 1] + P::col_count[M0 + CNT - 1];
   if constexpr (last > first) {
-    constexpr int line0 = first / 8, line1 = (last + 7) / 8;  // 8 doubles per line (64-byte aligned table)
-    for (int line = line0 + wave; line < line1; line += nwaves) {
-      const double* kp = kv + line * 8;
-      asm volatile("" : "+s"(kp));
-      use_s(*(const ConstDouble*)kp);
-    }
+    constexpr int line0 = first / 8, line1 = (last + 7) / 8;
+    constexpr int per_wave = (line1 - line0 + NWAVES - 1) / NWAVES;
+    const double* kp = kv + (line0 + wave) * 8;
+    asm volatile("" : "+s"(kp));
+    const ConstUint* kc = (const ConstUint*)kp;
+    const int avail = line1 - line0 - wave;  // lines this wave may touch: k * NWAVES < avail
+    unsigned v[per_wave];
+#pragma unroll
+    for (int k = 0; k < per_wave; ++k) v[k] = (k * NWAVES < avail) ? kc[k * NWAVES * 16] : 0u;
+#pragma unroll
+    for (int k = 0; k < per_wave; ++k) asm volatile("" ::"s"(v[k]));
   }
 }
 
@@ -386,15 +392,27 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
     static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
       constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
       constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
-      if constexpr (g > 0) prefetch_columns<N, m0, c>(kv, wave, kThreads / 64);
+      if constexpr (g > 0) prefetch_columns<N, m0, c, kThreads / 64>(kv, wave);
       // 1. right-hand side of the chunk to LDS; the top block has received
       //    no update yet: b = Q0 (S^-1 w), copied straight from memory
       if constexpr (g == N) {
-        for (int i = tid; i < nloc * kNQ * c * T; i += kThreads) {
-          const int ee = i / (kNQ * c * T), r = i % (kNQ * c * T);
-          const int pp = r / (c * T), kk = (r / T) % c, uu = r % T;
-          bufB[(ee * kNQ + pp) * C::S + kk * T + uu] =
-              static_cast<R>(a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] * sinv_w(uu));
+        constexpr int per_thread = (kE * kNQ * c + kThreads - 1) / kThreads;
+        double q[per_thread];
+#pragma unroll
+        for (int k = 0; k < per_thread; ++k) {
+          const int i = tid + k * kThreads;
+          const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+          q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < per_thread; ++k) {
+          const int i = tid + k * kThreads;
+          const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+          if (ee < nloc) {
+#pragma unroll
+            for (int uu = 0; uu < T; ++uu)
+              bufB[(ee * kNQ + pp) * C::S + kk * T + uu] = static_cast<R>(q[k] * sinv_w(uu));
+          }
         }
       } else {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
@@ -407,19 +425,38 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
 #pragma unroll
       for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
       if (closure) {
-        double drr[T];
+        // X of this lane, stored to memory right away (runs of T doubles
+        // per (element, quantity) and mode; consecutive modes complete
+        // the cache lines)
+        double* Qd = a.Q + ((e0 + es) * kNQ + p) * (B * T) + m0 * T + u;
+        double* Id = a.Qint ? a.Qint + ((e0 + es) * kNQ + p) * B + m0 : nullptr;
+        if (pb != cb) {
+          double drr[T];
 #pragma unroll
-        for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
-        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-          constexpr int kk = decltype(k)::value;
-          double x = 0.0;
+          for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
+          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+            constexpr int kk = decltype(k)::value;
+            double x = 0.0;
 #pragma unroll
-          for (int v = 0; v < T; ++v) {
-            x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
-            x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
-          }
-          bufX[cb + kk * T + u] = static_cast<R>(x);
-        });
+            for (int v = 0; v < T; ++v) {
+              x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+              x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
+            }
+            bufX[cb + kk * T + u] = static_cast<R>(x);
+            if (active) Qd[kk * T] = x;
+            if (active && Id && u == 0) Id[kk] = a.dt * x;
+          });
+        } else {
+          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+            constexpr int kk = decltype(k)::value;
+            double x = 0.0;
+#pragma unroll
+            for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+            bufX[cb + kk * T + u] = static_cast<R>(x);
+            if (active) Qd[kk * T] = x;
+            if (active && Id && u == 0) Id[kk] = a.dt * x;
+          });
+        }
       } else {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
@@ -487,8 +524,9 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
           __builtin_amdgcn_sched_barrier(0);
         });
       }
-      // 4. the chunk's space-time DOFs to memory (coalesced runs of c*T)
-      {
+      // 4. general E: the chunk's space-time DOFs to memory (coalesced runs
+      //    of c*T) once every level is final
+      if (!closure) {
         double* Qg = a.Q + e0 * (kNQ * B * T);
         constexpr int per = c * T;
         for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
