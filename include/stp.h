@@ -92,9 +92,10 @@ typedef enum stp_precision {
 stp_status stp_create(stp_handle* handle);
 stp_status stp_destroy(stp_handle handle);
 
-/* Bytes of device workspace stp_predict needs for these arguments
- * (currently 0 for every path: all intermediates live in registers, LDS or
- * the output buffer Q). */
+/* Bytes of device workspace stp_predict needs for these arguments: 0 for
+ * STP_FP64 (all intermediates live in registers, LDS or the output Q); for
+ * STP_FP32_REFINE with refine_steps > 0, the float residual of every element
+ * (n * 13 * B * T * 4 bytes, rounded up to 256). */
 stp_status stp_workspace_size(stp_handle handle, int degree, int64_t n_elements,
                               stp_precision precision, int refine_steps,
                               size_t* bytes);
@@ -114,6 +115,9 @@ stp_status stp_workspace_size(stp_handle handle, int degree, int64_t n_elements,
  *   Qint [n][13][B]      out: dt * time average over the step; may be NULL.
  * dt > 0 and finite (one time step for every element of the call).
  * refine_steps in 0..STP_MAX_REFINE (ignored for STP_FP64).
+ * workspace: device buffer of at least stp_workspace_size bytes (may be NULL
+ * when that size is 0), owned by the caller, contents ignored and clobbered;
+ * too small -> STP_EWORKSPACE.
  * n_elements == 0 is a no-op returning STP_OK. */
 stp_status stp_predict(stp_handle handle, void* hip_stream, int degree,
                        int64_t n_elements, double dt, const double* star,

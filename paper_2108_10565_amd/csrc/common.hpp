@@ -38,32 +38,41 @@ struct PredictArgs {
   double* Qint;          // [n][13][B] or nullptr
 };
 
+// Bytes of workspace the mixed-precision path needs: the float residual of
+// every element between the residual and the correction kernels.
+inline size_t workspace_bytes(int N, int64_t n, int precision, int refine_steps) {
+  if (precision == 0 || refine_steps == 0 || n <= 0) return 0;
+  const size_t raw = static_cast<size_t>(n) * kNQ * n_modes(N) * (N + 1) * sizeof(float);
+  return (raw + 255) / 256 * 256;
+}
+
 // Launchers (one per kernel family); return hipSuccess or the launch error.
 hipError_t launch_reference_kernel(int N, const PredictArgs& a, hipStream_t stream);
 // The fused kernel is compiled once per degree (STP_DEGREE); each object
 // defines the specialisation for its degree.
 template <int N>
-hipError_t launch_fused_degree(const PredictArgs& a, int precision, int refine_steps, hipStream_t stream);
-template <> hipError_t launch_fused_degree<0>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<1>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<2>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<3>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<4>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<5>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<6>(const PredictArgs&, int, int, hipStream_t);
-template <> hipError_t launch_fused_degree<7>(const PredictArgs&, int, int, hipStream_t);
+hipError_t launch_fused_degree(const PredictArgs& a, int precision, int refine_steps, float* workspace,
+                               hipStream_t stream);
+template <> hipError_t launch_fused_degree<0>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<1>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<2>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<3>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<4>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<5>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<6>(const PredictArgs&, int, int, float*, hipStream_t);
+template <> hipError_t launch_fused_degree<7>(const PredictArgs&, int, int, float*, hipStream_t);
 
 inline hipError_t launch_fused_kernel(int N, const PredictArgs& a, int precision, int refine_steps,
-                                      hipStream_t stream) {
+                                      float* workspace, hipStream_t stream) {
   switch (N) {
-    case 0: return launch_fused_degree<0>(a, precision, refine_steps, stream);
-    case 1: return launch_fused_degree<1>(a, precision, refine_steps, stream);
-    case 2: return launch_fused_degree<2>(a, precision, refine_steps, stream);
-    case 3: return launch_fused_degree<3>(a, precision, refine_steps, stream);
-    case 4: return launch_fused_degree<4>(a, precision, refine_steps, stream);
-    case 5: return launch_fused_degree<5>(a, precision, refine_steps, stream);
-    case 6: return launch_fused_degree<6>(a, precision, refine_steps, stream);
-    case 7: return launch_fused_degree<7>(a, precision, refine_steps, stream);
+    case 0: return launch_fused_degree<0>(a, precision, refine_steps, workspace, stream);
+    case 1: return launch_fused_degree<1>(a, precision, refine_steps, workspace, stream);
+    case 2: return launch_fused_degree<2>(a, precision, refine_steps, workspace, stream);
+    case 3: return launch_fused_degree<3>(a, precision, refine_steps, workspace, stream);
+    case 4: return launch_fused_degree<4>(a, precision, refine_steps, workspace, stream);
+    case 5: return launch_fused_degree<5>(a, precision, refine_steps, workspace, stream);
+    case 6: return launch_fused_degree<6>(a, precision, refine_steps, workspace, stream);
+    case 7: return launch_fused_degree<7>(a, precision, refine_steps, workspace, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -116,21 +116,6 @@ struct Shared {
   } u;
 };
 
-// The usage-ordered Khat table of degree N.  Kernels pass its address through
-// an empty asm statement before reading it, so the compiler cannot fold the
-// values into instruction literals and reads them with scalar loads instead.
-template <int N>
-__device__ __forceinline__ const double* khat_sparse() {
-  if constexpr (N == 0) return stp_gen::kKhatSparse0;
-  else if constexpr (N == 1) return stp_gen::kKhatSparse1;
-  else if constexpr (N == 2) return stp_gen::kKhatSparse2;
-  else if constexpr (N == 3) return stp_gen::kKhatSparse3;
-  else if constexpr (N == 4) return stp_gen::kKhatSparse4;
-  else if constexpr (N == 5) return stp_gen::kKhatSparse5;
-  else if constexpr (N == 6) return stp_gen::kKhatSparse6;
-  else return stp_gen::kKhatSparse7;
-}
-
 // Solves (Z - z I)^T y = rhs by Gauss-Jordan elimination without pivoting
 // (the eigenvalues of Z have real part >= 1, so for z <= 0.5 the pivots stay
 // away from zero; accurate to ~1e-15 there).  With rhs = e_s, y is row s of
@@ -161,23 +146,54 @@ __device__ __forceinline__ void zt_solve(double z, const double (&rhs)[T], doubl
   for (int r = 0; r < T; ++r) out[r] = a[r][T];
 }
 
+// The usage-ordered Khat table of degree N in precision R.  Kernels pass its
+// address through an empty asm statement before reading it, so the compiler
+// cannot fold the values into instruction literals and reads them with
+// scalar loads instead.
+template <int N, typename R>
+__device__ __forceinline__ const R* khat_sparse() {
+  if constexpr (sizeof(R) == 8) {
+    if constexpr (N == 0) return stp_gen::kKhatSparse0;
+    else if constexpr (N == 1) return stp_gen::kKhatSparse1;
+    else if constexpr (N == 2) return stp_gen::kKhatSparse2;
+    else if constexpr (N == 3) return stp_gen::kKhatSparse3;
+    else if constexpr (N == 4) return stp_gen::kKhatSparse4;
+    else if constexpr (N == 5) return stp_gen::kKhatSparse5;
+    else if constexpr (N == 6) return stp_gen::kKhatSparse6;
+    else return stp_gen::kKhatSparse7;
+  } else {
+    if constexpr (N == 0) return stp_gen::kKhatSparseF0;
+    else if constexpr (N == 1) return stp_gen::kKhatSparseF1;
+    else if constexpr (N == 2) return stp_gen::kKhatSparseF2;
+    else if constexpr (N == 3) return stp_gen::kKhatSparseF3;
+    else if constexpr (N == 4) return stp_gen::kKhatSparseF4;
+    else if constexpr (N == 5) return stp_gen::kKhatSparseF5;
+    else if constexpr (N == 6) return stp_gen::kKhatSparseF6;
+    else return stp_gen::kKhatSparseF7;
+  }
+}
+
 // Register pinning: an empty asm statement that reads (or reads and writes)
 // a register value.  Volatile asm statements keep their program order, so
 // these fix where a value must be complete and stop the compiler from
 // sinking pure arithmetic or hoisting loads across them.
 template <typename T>
 __device__ __forceinline__ void pin_v(T& x) { asm volatile("" : "+v"(x)); }
-__device__ __forceinline__ void use_s(double x) { asm volatile("" ::"s"(x)); }
+template <typename T>
+__device__ __forceinline__ void use_s(T x) { asm volatile("" ::"s"(x)); }
 
-constexpr int kGroup = 8;  // coefficients per scalar load (s_load_dwordx16)
+// Coefficients per scalar load: one s_load_dwordx16 (64 bytes).
+template <typename R>
+constexpr int kGroup = 64 / static_cast<int>(sizeof(R));
 
 // Loads the coefficients [g0, g0 + gn) of the usage-ordered Khat table into
 // scalar registers, from an address the compiler cannot see through.
-template <int g0, int gn>
-__device__ __forceinline__ void load_group(const double* kv, double (&v)[kGroup]) {
-  const double* kp = kv + g0;
+template <typename R, int g0, int gn>
+__device__ __forceinline__ void load_group(const R* kv, R (&v)[kGroup<R>]) {
+  using CR = __attribute__((address_space(4))) const R;
+  const R* kp = kv + g0;
   asm volatile("" : "+s"(kp));
-  const ConstDouble* kc = (const ConstDouble*)kp;
+  const CR* kc = (const CR*)kp;
 #pragma unroll
   for (int i = 0; i < gn; ++i) v[i] = kc[i];
 }
@@ -187,15 +203,16 @@ __device__ __forceinline__ void load_group(const double* kv, double (&v)[kGroup]
 // range (64-byte lines, table 64-byte aligned), issuing every load before
 // waiting once, so the line fetches overlap each other and the other waves'
 // work; the per-group loads of the green update then hit the cache.
-template <int N, int M0, int CNT, int NWAVES>
-__device__ __forceinline__ void prefetch_columns(const double* kv, int wave) {
+template <int N, typename R, int M0, int CNT, int NWAVES>
+__device__ __forceinline__ void prefetch_columns(const R* kv, int wave) {
   using P = stp_gen::KhatPattern<N>;
+  constexpr int per_line = 64 / static_cast<int>(sizeof(R));
   constexpr int first = P::col_start[M0];
   constexpr int last = P::col_start[M0 + CNT - 1] + P::col_count[M0 + CNT - 1];
   if constexpr (last > first) {
-    constexpr int line0 = first / 8, line1 = (last + 7) / 8;
+    constexpr int line0 = first / per_line, line1 = (last + per_line - 1) / per_line;
     constexpr int per_wave = (line1 - line0 + NWAVES - 1) / NWAVES;
-    const double* kp = kv + (line0 + wave) * 8;
+    const R* kp = kv + (line0 + wave) * per_line;
     asm volatile("" : "+s"(kp));
     const ConstUint* kc = (const ConstUint*)kp;
     const int avail = line1 - line0 - wave;  // lines this wave may touch: k * NWAVES < avail
@@ -208,34 +225,34 @@ __device__ __forceinline__ void prefetch_columns(const double* kv, int wave) {
 }
 
 // b[n] -= Khat^j[n, M] y_j for the non-zeros of column M (usage order of the
-// generated pattern: directions, then rows ascending), in groups of kGroup
-// coefficients; the next group's scalar load is issued before the current
-// group's fused multiply-adds and waited for after them.
+// generated pattern: directions, then rows ascending), in groups of
+// kGroup<R> coefficients; the next group's scalar load is issued before the
+// current group's fused multiply-adds and waited for after them.
 template <int N, int M, typename R>
-__device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y2, const double* kv) {
+__device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y2, const R* kv) {
   using P = stp_gen::KhatPattern<N>;
+  constexpr int GS = kGroup<R>;
   constexpr int start = P::col_start[M];
   constexpr int count = P::col_count[M];
-  constexpr int ngroups = (count + kGroup - 1) / kGroup;
+  constexpr int ngroups = (count + GS - 1) / GS;
   if constexpr (count > 0) {
-    double cur[kGroup], nxt[kGroup];
-    load_group<start, (count < kGroup ? count : kGroup)>(kv, cur);
+    R cur[GS], nxt[GS];
+    load_group<R, start, (count < GS ? count : GS)>(kv, cur);
 #pragma unroll
-    for (int i = 0; i < (count < kGroup ? count : kGroup); ++i) use_s(cur[i]);
+    for (int i = 0; i < (count < GS ? count : GS); ++i) use_s(cur[i]);
     static_for<0, ngroups>([&](auto G) __attribute__((always_inline)) {
       constexpr int gi = decltype(G)::value;
-      constexpr int g0 = start + gi * kGroup;
-      constexpr int gn = (start + count - g0) < kGroup ? (start + count - g0) : kGroup;
-      constexpr int g1 = g0 + kGroup;
-      constexpr int gn1 = (start + count - g1) < kGroup ? (start + count - g1) : kGroup;
-      if constexpr (gi + 1 < ngroups) load_group<g1, gn1>(kv, nxt);
+      constexpr int g0 = start + gi * GS;
+      constexpr int gn = (start + count - g0) < GS ? (start + count - g0) : GS;
+      constexpr int g1 = g0 + GS;
+      constexpr int gn1 = (start + count - g1) < GS ? (start + count - g1) : GS;
+      if constexpr (gi + 1 < ngroups) load_group<R, g1, gn1>(kv, nxt);
       static_for<0, gn>([&](auto I) __attribute__((always_inline)) {
         constexpr int e = g0 + decltype(I)::value;
         constexpr int n = P::row[e];
         constexpr int j = P::dir[e];
-        const R k = static_cast<R>(cur[decltype(I)::value]);
         const R y = (j == 0) ? y0 : ((j == 1) ? y1 : y2);
-        b[n] = fma(-k, y, b[n]);
+        b[n] = fma(-cur[decltype(I)::value], y, b[n]);
       });
       static_for<0, gn>([&](auto I) __attribute__((always_inline)) {
         pin_v(b[P::row[g0 + decltype(I)::value]]);
@@ -251,10 +268,167 @@ __device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArgs a) {
+// Modes of the solve kernel.
+constexpr int kInit = 0;     // b = Q0 (S^-1 w); Q <- X
+constexpr int kCorrect = 1;  // b = residual (float workspace); Q <- Q + X
+
+// Per-lane setup shared by the solve and residual kernels: stages E* and
+// A^{j*} of the group, derives the dependency levels of the strict upper part
+// G of E*, row u of (Z - E*_pp I)^-1 (to LDS), the sparse star row, the G
+// coupling of the lane's quantity and the closure row dr (to LDS).
+template <int N, typename R>
+struct LaneSetup {
   using C = Cfg<N>;
-  using R = double;
+  R sa0[kStarNnz], sa1[kStarNnz], sa2[kStarNnz];
+  int sq[kStarNnz];
+  int gp, gcount;
+  double gcoef;
+  bool dense_star, closure;
+  int maxlevel, mylevel;
+
+  __device__ __forceinline__ void run(Shared<N, R>& sh, const PredictArgs& a, int64_t e0, int nloc, int tid,
+                                      int es, int p, int u, bool active, int cb) {
+    constexpr int kThreads = C::kThreads, T = C::T;
+    for (int i = tid; i < C::kSlots * kNQ * kNQ; i += kThreads) {
+      const int r = (i / kNQ) % kNQ, c = i % kNQ;
+      (&sh.G[0][0][0])[i] = (i < nloc * kNQ * kNQ && c >= r) ? a.dt * a.E[e0 * (kNQ * kNQ) + i] : 0.0;
+    }
+    for (int i = tid; i < C::kSlots * 3 * kNQ * kNQ; i += kThreads)
+      (&sh.u.A[0][0][0][0])[i] = i < nloc * 3 * kNQ * kNQ ? a.dt * a.star[e0 * (3 * kNQ * kNQ) + i] : 0.0;
+    if (tid == 0) sh.maxlevel = 0;
+    __syncthreads();
+    // dependency levels, one thread per element
+    if (tid < nloc) {
+      int lev[kNQ];
+      int mx = 0;
+#pragma unroll
+      for (int o = kNQ - 1; o >= 0; --o) {
+        int l = 0;
+#pragma unroll
+        for (int q = o + 1; q < kNQ; ++q)
+          if (sh.G[tid][o][q] != 0.0 && lev[q] + 1 > l) l = lev[q] + 1;
+        lev[o] = l;
+        sh.level[tid][o] = l;
+        mx = l > mx ? l : mx;
+      }
+      atomicMax(&sh.maxlevel, mx);
+    }
+    // row u of (Z - E*_pp I)^-1
+    double zr[T];
+    {
+      double e_u[T];
+#pragma unroll
+      for (int v = 0; v < T; ++v) e_u[v] = (v == u) ? 1.0 : 0.0;
+      zt_solve<T>(sh.G[es][p][p], e_u, zr);
+#pragma unroll
+      for (int v = 0; v < T; ++v) sh.zr[tid][v] = zr[v];
+    }
+    // sparse row p of the three star matrices
+    bool overflow = false;
+    {
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < kStarNnz; ++k) {
+        sa0[k] = sa1[k] = sa2[k] = R(0);
+        sq[k] = cb + u;
+      }
+#pragma unroll
+      for (int q = 0; q < kNQ; ++q) {
+        const double v0 = sh.u.A[es][0][p][q], v1 = sh.u.A[es][1][p][q], v2 = sh.u.A[es][2][p][q];
+        if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
+#pragma unroll
+          for (int k = 0; k < kStarNnz; ++k)
+            if (k == cnt) {
+              sa0[k] = static_cast<R>(v0);
+              sa1[k] = static_cast<R>(v1);
+              sa2[k] = static_cast<R>(v2);
+              sq[k] = (es * kNQ + q) * C::S + u;
+            }
+          ++cnt;
+        }
+      }
+      overflow = active && cnt > kStarNnz;
+    }
+    // G coupling of this lane's quantity
+    gcount = 0;
+    gp = p;
+    gcoef = 0.0;
+    for (int q = p + 1; q < kNQ; ++q) {
+      const double gq = sh.G[es][p][q];
+      if (gq != 0.0) {
+        if (gcount == 0) {
+          gcoef = gq;
+          gp = q;
+        }
+        ++gcount;
+      }
+    }
+    // uniform over the workgroup: scalar branches, no exec masking.  This
+    // barrier also orders the reads of A before the chunk buffers (which share
+    // its storage) are written.
+    dense_star = __builtin_amdgcn_readfirstlane(__syncthreads_or(overflow)) != 0;
+    maxlevel = sh.maxlevel;
+    mylevel = active ? sh.level[es][p] : 0;
+    const int gp_level = active ? sh.level[es][gp] : 0;
+    // closure form of the coupling when every coupled quantity couples to one
+    // quantity that itself is uncoupled (the poroelastic case):
+    //   X_o = Zinv_o (b_o + g X_p) = zr . b_o + dr . b_p,
+    //   dr = g * (row of Zinv_o) * Zinv_p, i.e. (Z - E*_pp I)^T dr = g zr
+    closure = __builtin_amdgcn_readfirstlane(
+                  __syncthreads_and(!active || (gcount <= 1 && (gcount == 0 || gp_level == 0)))) != 0;
+    {
+      double dr[T];
+      if (gcount == 1 && closure) {
+        double rhs[T];
+#pragma unroll
+        for (int v = 0; v < T; ++v) rhs[v] = gcoef * zr[v];
+        zt_solve<T>(sh.G[es][gp][gp], rhs, dr);
+      } else {
+#pragma unroll
+        for (int v = 0; v < T; ++v) dr[v] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < T; ++v) sh.dr[tid][v] = dr[v];
+    }
+  }
+
+  // y_j = (A^{j*} X[:, m, u])_p for j = 1..3 from the chunk buffer
+  template <int kk>
+  __device__ __forceinline__ void star(const R* bufX, const PredictArgs& a, int64_t e0, int es, int p, int u,
+                                       bool active, R& y0, R& y1, R& y2) const {
+    constexpr int T = C::T;
+    y0 = y1 = y2 = R(0);
+    // opaque per-mode offset: this mode's LDS reads stay here
+    int xoff = kk * T;
+    asm volatile("" : "+v"(xoff));
+    const R* xs = bufX + xoff;
+    if (!dense_star) {
+#pragma unroll
+      for (int k = 0; k < kStarNnz; ++k) {
+        const R xq = xs[sq[k]];
+        y0 = fma(sa0[k], xq, y0);
+        y1 = fma(sa1[k], xq, y1);
+        y2 = fma(sa2[k], xq, y2);
+      }
+    } else {
+      const double* st = a.star + (active ? e0 + es : 0) * (3 * kNQ * kNQ) + p * kNQ;
+#pragma unroll
+      for (int q = 0; q < kNQ; ++q) {
+        const R xq = xs[(es * kNQ + q) * C::S + u];
+        y0 = fma(static_cast<R>(a.dt * st[q]), xq, y0);
+        y1 = fma(static_cast<R>(a.dt * st[kNQ * kNQ + q]), xq, y1);
+        y2 = fma(static_cast<R>(a.dt * st[2 * kNQ * kNQ + q]), xq, y2);
+      }
+    }
+  }
+};
+
+// Algorithm 3 over a group of elements in precision R (the dark-blue solves
+// are float64 in every mode).  kInit: b = Q0 (S^-1 w), Q <- X.  kCorrect:
+// b = the residual in `rin` (float), Q <- Q + X.
+template <int N, typename R, int Mode>
+__global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictArgs a, const float* rin) {
+  using C = Cfg<N>;
   constexpr int B = C::B, T = C::T, kE = C::kElems, kThreads = C::kThreads;
   __shared__ Shared<N, R> sh;
   R* const bufB = sh.u.c.bufB;
@@ -270,148 +444,61 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
   const int p = col / T, u = col % T;
   const bool active = es < nloc;
   const int cb = (es * kNQ + p) * C::S;  // this lane's (element, quantity) block in bufB / bufX
-  const double* kv = khat_sparse<N>();
+  const R* kv = khat_sparse<N, R>();
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);  // (element, quantity) row of this lane
 
-  // ---- stage E* and A^{j*} of the group (coalesced)
-  for (int i = tid; i < C::kSlots * kNQ * kNQ; i += kThreads) {
-    const int r = (i / kNQ) % kNQ, c = i % kNQ;
-    (&sh.G[0][0][0])[i] = (i < nloc * kNQ * kNQ && c >= r) ? a.dt * a.E[e0 * (kNQ * kNQ) + i] : 0.0;
-  }
-  for (int i = tid; i < C::kSlots * 3 * kNQ * kNQ; i += kThreads)
-    (&sh.u.A[0][0][0][0])[i] = i < nloc * 3 * kNQ * kNQ ? a.dt * a.star[e0 * (3 * kNQ * kNQ) + i] : 0.0;
-  if (tid == 0) sh.maxlevel = 0;
-  // register rows of b: b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
+  // register rows of b below the top block
   R b[C::LR];
-  {
+  if constexpr (Mode == kInit) {
+    // b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
     const double w = sinv_w(u);
-    const double* q0row = a.Q0 + ((active ? e0 + es : 0) * kNQ + p) * B;
+    const double* q0row = a.Q0 + erow * B;
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w);
+  } else {
+    const float* rrow = rin + erow * (B * T) + u;
+#pragma unroll
+    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(rrow[n * T]);
   }
-  __syncthreads();
-
-  // ---- dependency levels of the strict upper part of E*, one thread per element
-  if (tid < nloc) {
-    int lev[kNQ];
-    int mx = 0;
-#pragma unroll
-    for (int o = kNQ - 1; o >= 0; --o) {
-      int l = 0;
-#pragma unroll
-      for (int q = o + 1; q < kNQ; ++q)
-        if (sh.G[tid][o][q] != 0.0 && lev[q] + 1 > l) l = lev[q] + 1;
-      lev[o] = l;
-      sh.level[tid][o] = l;
-      mx = l > mx ? l : mx;
-    }
-    atomicMax(&sh.maxlevel, mx);
-  }
-  // ---- row u of (Z - E*_pp I)^-1 (kept in LDS, loaded for the dark-blue step)
-  double zr[T];
-  {
-    double e_u[T];
-#pragma unroll
-    for (int v = 0; v < T; ++v) e_u[v] = (v == u) ? 1.0 : 0.0;
-    zt_solve<T>(sh.G[es][p][p], e_u, zr);
-#pragma unroll
-    for (int v = 0; v < T; ++v) sh.zr[tid][v] = zr[v];
-  }
-  // ---- sparse row p of the three star matrices
-  double sa0[kStarNnz], sa1[kStarNnz], sa2[kStarNnz];
-  int sq[kStarNnz];
-  bool overflow = false;
-  {
-    int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kStarNnz; ++k) {
-      sa0[k] = sa1[k] = sa2[k] = 0.0;
-      sq[k] = cb + u;
-    }
-#pragma unroll
-    for (int q = 0; q < kNQ; ++q) {
-      const double v0 = sh.u.A[es][0][p][q], v1 = sh.u.A[es][1][p][q], v2 = sh.u.A[es][2][p][q];
-      if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
-#pragma unroll
-        for (int k = 0; k < kStarNnz; ++k)
-          if (k == cnt) {
-            sa0[k] = v0;
-            sa1[k] = v1;
-            sa2[k] = v2;
-            sq[k] = (es * kNQ + q) * C::S + u;
-          }
-        ++cnt;
-      }
-    }
-    overflow = active && cnt > kStarNnz;
-  }
-  // ---- G coupling of this lane's quantity
-  int gcount = 0, gp = p;
-  double gcoef = 0.0;
-  for (int q = p + 1; q < kNQ; ++q) {
-    const double gq = sh.G[es][p][q];
-    if (gq != 0.0) {
-      if (gcount == 0) {
-        gcoef = gq;
-        gp = q;
-      }
-      ++gcount;
-    }
-  }
-  // uniform over the workgroup: scalar branches, no exec masking.  This
-  // barrier also orders the setup's reads of A before the chunk buffers
-  // (which share its storage) are written.
-  const bool dense_star = __builtin_amdgcn_readfirstlane(__syncthreads_or(overflow)) != 0;
-  const int maxlevel = sh.maxlevel;
-  const int mylevel = active ? sh.level[es][p] : 0;
-  const int gp_level = active ? sh.level[es][gp] : 0;
-  // closure form of the coupling when every coupled quantity couples to one
-  // quantity that itself is uncoupled (the poroelastic case):
-  //   X_o = Zinv_o (b_o + g X_p) = zr . b_o + dr . b_p,
-  //   dr = g * (row of Zinv_o) * Zinv_p, i.e. (Z - E*_pp I)^T dr = g zr
-  const bool closure = __builtin_amdgcn_readfirstlane(
-                           __syncthreads_and(!active || (gcount <= 1 && (gcount == 0 || gp_level == 0)))) != 0;
-  const int pb = (es * kNQ + gp) * C::S;  // block of the coupled quantity (own block if uncoupled)
-  {
-    double dr[T];
-    if (gcount == 1 && closure) {
-      double rhs[T];
-#pragma unroll
-      for (int v = 0; v < T; ++v) rhs[v] = gcoef * zr[v];
-      zt_solve<T>(sh.G[es][gp][gp], rhs, dr);
-    } else {
-#pragma unroll
-      for (int v = 0; v < T; ++v) dr[v] = 0.0;
-    }
-#pragma unroll
-    for (int v = 0; v < T; ++v) sh.dr[tid][v] = dr[v];
-  }
+  LaneSetup<N, R> L;
+  L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
+  const int pb = (es * kNQ + L.gp) * C::S;  // block of the coupled quantity (own block if uncoupled)
 
   static_for<0, N + 1>([&](auto gi) __attribute__((always_inline)) {
     constexpr int g = N - decltype(gi)::value;
     static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
       constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
       constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
-      if constexpr (g > 0) prefetch_columns<N, m0, c, kThreads / 64>(kv, wave);
-      // 1. right-hand side of the chunk to LDS; the top block has received
-      //    no update yet: b = Q0 (S^-1 w), copied straight from memory
+      if constexpr (g > 0) prefetch_columns<N, R, m0, c, kThreads / 64>(kv, wave);
+      // 1. right-hand side of the chunk to LDS; the top block has received no
+      //    update yet, so it comes straight from memory
       if constexpr (g == N) {
-        constexpr int per_thread = (kE * kNQ * c + kThreads - 1) / kThreads;
-        double q[per_thread];
+        if constexpr (Mode == kInit) {
+          constexpr int per_thread = (kE * kNQ * c + kThreads - 1) / kThreads;
+          double q[per_thread];
 #pragma unroll
-        for (int k = 0; k < per_thread; ++k) {
-          const int i = tid + k * kThreads;
-          const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
-          q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
-        }
+          for (int k = 0; k < per_thread; ++k) {
+            const int i = tid + k * kThreads;
+            const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+            q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
+          }
 #pragma unroll
-        for (int k = 0; k < per_thread; ++k) {
-          const int i = tid + k * kThreads;
-          const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
-          if (ee < nloc) {
+          for (int k = 0; k < per_thread; ++k) {
+            const int i = tid + k * kThreads;
+            const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+            if (ee < nloc) {
 #pragma unroll
-            for (int uu = 0; uu < T; ++uu)
-              bufB[(ee * kNQ + pp) * C::S + kk * T + uu] = static_cast<R>(q[k] * sinv_w(uu));
+              for (int uu = 0; uu < T; ++uu)
+                bufB[(ee * kNQ + pp) * C::S + kk * T + uu] = static_cast<R>(q[k] * sinv_w(uu));
+            }
+          }
+        } else {
+          constexpr int per = c * T;
+          for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
+            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
+            const int pp = rem / per, r = rem % per;
+            bufB[(ee * kNQ + pp) * C::S + r] = static_cast<R>(rin[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + r]);
           }
         }
       } else {
@@ -420,43 +507,35 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
         });
       }
       __syncthreads();
-      // 2. dark-blue blocks and G coupling
+      // 2. dark-blue blocks and G coupling (float64)
       double zr[T];
 #pragma unroll
       for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
-      if (closure) {
-        // X of this lane, stored to memory right away (runs of T doubles
-        // per (element, quantity) and mode; consecutive modes complete
-        // the cache lines)
-        double* Qd = a.Q + ((e0 + es) * kNQ + p) * (B * T) + m0 * T + u;
-        double* Id = a.Qint ? a.Qint + ((e0 + es) * kNQ + p) * B + m0 : nullptr;
-        if (pb != cb) {
-          double drr[T];
+      constexpr bool direct_store = (Mode == kInit);
+      if (L.closure) {
+        // X of this lane; in kInit mode stored to memory right away (runs of
+        // T doubles per (element, quantity) and mode)
+        double* Qd = a.Q + erow * (B * T) + m0 * T + u;
+        double* Id = a.Qint ? a.Qint + erow * B + m0 : nullptr;
+        // every lane reads its own and its coupled quantity's column (its
+        // own again, with dr = 0, when uncoupled): no divergent branch
+        double drr[T];
 #pragma unroll
-          for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
-          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-            constexpr int kk = decltype(k)::value;
-            double x = 0.0;
+        for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
+        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+          constexpr int kk = decltype(k)::value;
+          double x = 0.0;
 #pragma unroll
-            for (int v = 0; v < T; ++v) {
-              x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
-              x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
-            }
-            bufX[cb + kk * T + u] = static_cast<R>(x);
+          for (int v = 0; v < T; ++v) {
+            x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+            x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
+          }
+          bufX[cb + kk * T + u] = static_cast<R>(x);
+          if constexpr (direct_store) {
             if (active) Qd[kk * T] = x;
             if (active && Id && u == 0) Id[kk] = a.dt * x;
-          });
-        } else {
-          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-            constexpr int kk = decltype(k)::value;
-            double x = 0.0;
-#pragma unroll
-            for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
-            bufX[cb + kk * T + u] = static_cast<R>(x);
-            if (active) Qd[kk * T] = x;
-            if (active && Id && u == 0) Id[kk] = a.dt * x;
-          });
-        }
+          }
+        });
       } else {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
@@ -467,9 +546,9 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
         });
         // general upper-triangular E: level by level, each level after the
         // levels it depends on
-        for (int r = 1; r <= maxlevel; ++r) {
+        for (int r = 1; r <= L.maxlevel; ++r) {
           __syncthreads();
-          if (mylevel == r) {
+          if (L.mylevel == r) {
             static_for<0, c>([&](auto k) __attribute__((always_inline)) {
               constexpr int kk = decltype(k)::value;
               double acc[T];
@@ -496,53 +575,133 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
       if constexpr (g > 0) {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
-          R y0 = 0, y1 = 0, y2 = 0;
-          // opaque per-mode offset: this mode's LDS reads stay here
-          int xoff = kk * T;
-          asm volatile("" : "+v"(xoff));
-          const R* xs = bufX + xoff;
-          if (!dense_star) {
-#pragma unroll
-            for (int k = 0; k < kStarNnz; ++k) {
-              const R xq = xs[sq[k]];
-              y0 = fma(static_cast<R>(sa0[k]), xq, y0);
-              y1 = fma(static_cast<R>(sa1[k]), xq, y1);
-              y2 = fma(static_cast<R>(sa2[k]), xq, y2);
-            }
-          } else {
-            const double* st = a.star + (active ? e0 + es : 0) * (3 * kNQ * kNQ) + p * kNQ;
-#pragma unroll
-            for (int q = 0; q < kNQ; ++q) {
-              const R xq = xs[(es * kNQ + q) * C::S + u];
-              y0 = fma(static_cast<R>(a.dt * st[q]), xq, y0);
-              y1 = fma(static_cast<R>(a.dt * st[kNQ * kNQ + q]), xq, y1);
-              y2 = fma(static_cast<R>(a.dt * st[2 * kNQ * kNQ + q]), xq, y2);
-            }
-          }
+          R y0, y1, y2;
+          L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
           green_column<N, m0 + kk, R>(b, y0, y1, y2, kv);
           // keep the scheduler from hoisting the next mode's LDS reads
           __builtin_amdgcn_sched_barrier(0);
         });
       }
-      // 4. general E: the chunk's space-time DOFs to memory (coalesced runs
-      //    of c*T) once every level is final
-      if (!closure) {
+      // 4. outputs not stored in step 2 (kCorrect, general E): coalesced runs
+      //    of c*T; Q <- X (kInit) or Q <- Q + X (kCorrect)
+      if (!(direct_store && L.closure)) {
         double* Qg = a.Q + e0 * (kNQ * B * T);
+        double* Ig = a.Qint ? a.Qint + e0 * (kNQ * B) : nullptr;
         constexpr int per = c * T;
         for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
           const int ee = i / (kNQ * per), rem = i % (kNQ * per);
           const int pp = rem / per, r = rem % per;
-          Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r] = bufX[(ee * kNQ + pp) * C::S + r];
+          double* q = &Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r];
+          double x = static_cast<double>(bufX[(ee * kNQ + pp) * C::S + r]);
+          if constexpr (Mode == kCorrect) x += *q;
+          *q = x;
+          if (Ig && r % T == 0) Ig[(ee * kNQ + pp) * B + m0 + r / T] = a.dt * x;
         }
-        if (a.Qint) {
-          double* Ig = a.Qint + e0 * (kNQ * B);
+      }
+    });
+  });
+}
+
+// Float64 residual of the full element system for the current Q (the
+// matrix-free form of eq:stp-lineq after the multiplication with M^-1 S^-1,
+// section "Block-wise back-substitution"):
+//   r[p,n,u] = (S^-1 w)_u Q0[p,n] - sum_s Z_us Q[p,n,s] + sum_q E*_pq Q[q,n,u]
+//              - sum_j sum_q A^{j*}_pq sum_l Khat^j[n,l] Q[q,l,u],
+// written to `rout` in float (the right-hand side of the correction solve).
+// Same lane mapping and chunk order as the solve; the Khat term is the green
+// update of the solve applied to the known Q, accumulated in float64.
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(PredictArgs a, float* rout) {
+  using C = Cfg<N>;
+  using R = double;
+  constexpr int B = C::B, T = C::T, kE = C::kElems, kThreads = C::kThreads;
+  __shared__ Shared<N, R> sh;
+  R* const bufB = sh.u.c.bufB;  // Q0 of the chunk (column 0 of each mode's block)
+  R* const bufX = sh.u.c.bufX;  // Q of the chunk
+  const int tid = threadIdx.x;
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
+  const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
+  const int nloc = static_cast<int>(nloc64);
+  const int es = (tid / C::kCols) < kE ? (tid / C::kCols) : kE;
+  const int col = tid % C::kCols;
+  const int p = col / T, u = col % T;
+  const bool active = es < nloc;
+  const int cb = (es * kNQ + p) * C::S;
+  const R* kv = khat_sparse<N, R>();
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);
+  const double w = sinv_w(u);
+
+  R r[C::LR];
+  {
+    const double* q0row = a.Q0 + erow * B;
+#pragma unroll
+    for (int n = 0; n < C::LN; ++n) r[n] = q0row[n] * w;
+  }
+  LaneSetup<N, R> L;
+  L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
+  const double zpp = sh.G[es][p][p];
+  const bool general_g = __builtin_amdgcn_readfirstlane(__syncthreads_or(active && L.gcount > 1)) != 0;
+  const int pb = (es * kNQ + L.gp) * C::S;
+  double zrow[T];  // row u of Z
+#pragma unroll
+  for (int v = 0; v < T; ++v) zrow[v] = z_entry(u, v);
+
+  static_for<0, N + 1>([&](auto gi) __attribute__((always_inline)) {
+    constexpr int g = N - decltype(gi)::value;
+    static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
+      constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
+      constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
+      if constexpr (g > 0) prefetch_columns<N, R, m0, c, kThreads / 64>(kv, wave);
+      // stage Q of the chunk (and Q0 of the top block) in LDS, coalesced
+      {
+        constexpr int per = c * T;
+        for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
+          const int ee = i / (kNQ * per), rem = i % (kNQ * per);
+          const int pp = rem / per, rr = rem % per;
+          bufX[(ee * kNQ + pp) * C::S + rr] = a.Q[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + rr];
+        }
+        if constexpr (g == N) {
           for (int i = tid; i < nloc * kNQ * c; i += kThreads) {
-            const int ee = i / (kNQ * c), rem = i % (kNQ * c);
-            const int pp = rem / c, kk = rem % c;
-            Ig[(ee * kNQ + pp) * B + m0 + kk] = a.dt * bufX[(ee * kNQ + pp) * C::S + kk * T];
+            const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+            bufB[(ee * kNQ + pp) * C::S + kk] = a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk];
           }
         }
       }
+      __syncthreads();
+      // local terms of the chunk's rows: their residual is now complete
+      static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+        constexpr int kk = decltype(k)::value;
+        constexpr int m = m0 + kk;
+        double base;
+        if constexpr (g == N) base = bufB[cb + kk] * w;
+        else base = r[m];
+        double zx = 0.0;
+#pragma unroll
+        for (int v = 0; v < T; ++v) zx = fma(zrow[v], bufX[cb + kk * T + v], zx);
+        double ex = zpp * bufX[cb + kk * T + u];
+        if (!general_g) {
+          ex = fma(L.gcoef, bufX[pb + kk * T + u], ex);
+        } else {
+          for (int q = p + 1; q < kNQ; ++q) {
+            const double gq = sh.G[es][p][q];
+            if (gq != 0.0) ex = fma(gq, bufX[(es * kNQ + q) * C::S + kk * T + u], ex);
+          }
+        }
+        const double res = base - zx + ex;
+        if (active) rout[erow * (B * T) + m * T + u] = static_cast<float>(res);
+      });
+      // Khat term into the rows of lower blocks
+      if constexpr (g > 0) {
+        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+          constexpr int kk = decltype(k)::value;
+          R y0, y1, y2;
+          L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
+          green_column<N, m0 + kk, R>(r, y0, y1, y2, kv);
+          __builtin_amdgcn_sched_barrier(0);
+        });
+      }
+      __syncthreads();  // before the next chunk overwrites the buffers
     });
   });
 }
@@ -551,15 +710,27 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_fp64_kernel(PredictArg
 
 template <>
 hipError_t launch_fused_degree<STP_DEGREE>(const PredictArgs& a, int precision, int refine_steps,
-                                           hipStream_t stream) {
+                                           float* workspace, hipStream_t stream) {
   constexpr int N = STP_DEGREE;
-  (void)refine_steps;
-  if (precision != 0) return hipErrorNotSupported;
-  const int64_t groups = (a.n + Cfg<N>::kElems - 1) / Cfg<N>::kElems;
+  using C = Cfg<N>;
+  const int64_t groups = (a.n + C::kElems - 1) / C::kElems;
   if (groups > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused_fp64_kernel<N>, dim3(static_cast<unsigned>(groups)), dim3(Cfg<N>::kThreads), 0,
-                     stream, a);
-  return hipGetLastError();
+  const dim3 grid(static_cast<unsigned>(groups)), block(C::kThreads);
+  if (precision == 0) {
+    hipLaunchKernelGGL((fused_solve_kernel<N, double, kInit>), grid, block, 0, stream, a, nullptr);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((fused_solve_kernel<N, float, kInit>), grid, block, 0, stream, a, nullptr);
+  hipError_t err = hipGetLastError();
+  for (int k = 0; k < refine_steps && err == hipSuccess; ++k) {
+    hipLaunchKernelGGL((fused_residual_kernel<N>), grid, block, 0, stream, a, workspace);
+    err = hipGetLastError();
+    if (err != hipSuccess) break;
+    hipLaunchKernelGGL((fused_solve_kernel<N, float, kCorrect>), grid, block, 0, stream, a,
+                       static_cast<const float*>(workspace));
+    err = hipGetLastError();
+  }
+  return err;
 }
 
 }  // namespace stp

@@ -85,7 +85,7 @@ stp_status stp_workspace_size(stp_handle handle, int degree, int64_t n_elements,
   if (n_elements < 0) return fail(handle, STP_EINVAL, "n_elements < 0");
   if (precision != STP_FP64 && precision != STP_FP32_REFINE) return fail(handle, STP_EINVAL, "precision");
   if (refine_steps < 0 || refine_steps > STP_MAX_REFINE) return fail(handle, STP_EINVAL, "refine_steps");
-  *bytes = 0;
+  *bytes = stp::workspace_bytes(degree, n_elements, static_cast<int>(precision), refine_steps);
   return STP_OK;
 }
 
@@ -93,8 +93,6 @@ stp_status stp_predict(stp_handle handle, void* hip_stream, int degree, int64_t 
                        const double* star, const double* E, const double* Q0, double* Q, double* Qint,
                        stp_precision precision, int refine_steps, void* workspace,
                        size_t workspace_bytes, unsigned flags) {
-  (void)workspace;
-  (void)workspace_bytes;
   stp_status st = check_common(handle, degree, n_elements, dt);
   if (st != STP_OK) return st;
   handle->last_error.clear();
@@ -107,13 +105,18 @@ stp_status stp_predict(stp_handle handle, void* hip_stream, int degree, int64_t 
     return fail(handle, STP_EINVAL, "the reference kernel is float64 only");
   if (n_elements == 0) return STP_OK;
   if (!star || !E || !Q0 || !Q) return fail(handle, STP_EINVAL, "NULL array pointer");
+  const size_t need = stp::workspace_bytes(degree, n_elements, static_cast<int>(precision), refine_steps);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(handle, STP_EWORKSPACE,
+                "workspace of " + std::to_string(need) + " bytes needed, got " + std::to_string(workspace_bytes));
   stp::PredictArgs a{n_elements, dt, star, E, Q0, Q, Qint};
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   hipError_t err;
   if (flags & STP_FLAG_REFERENCE_KERNEL)
     err = stp::launch_reference_kernel(degree, a, stream);
   else
-    err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps, stream);
+    err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps,
+                                   static_cast<float*>(workspace), stream);
   if (err != hipSuccess) return hip_fail(handle, err, "kernel launch");
   return STP_OK;
 }
