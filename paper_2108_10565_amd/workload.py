@@ -221,14 +221,28 @@ def _materials(kind, rng, n):
     return mat
 
 
-def _chunk(seed, c, kind, N, count):
+def _chunk(seed, c, kind, N, count, dt=None):
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, c])))
-    mat = _materials(kind, rng, count)
+    mat = _materials("homogeneous" if kind == "homogeneous" else "heterogeneous", rng, count)
     A, B, C, E = jacobians(mat)
     v = random_tets(rng, count)
     star = star_matrices(A, B, C, v)
     Q0 = rng.standard_normal((count, NQ, n_modes(N)))
     cfl = insphere_diameter(v) / max_wave_speed(A)
+    if kind == "stiffness" and dt is not None:
+        # stiffness sweep: target z = dt |E_uf,uf| log-uniform in [1e-2, 1e6]
+        # and viscosity log-uniform in [1e-3, 1e-1]; the permeability follows
+        # from |E_uf,uf| = rho nu / (kappa D).  Wave speeds (and so dt) do not
+        # depend on kappa or nu.
+        r2 = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, c, 1])))
+        z = 10.0 ** r2.uniform(-2.0, 6.0, count)
+        nu = 10.0 ** r2.uniform(-3.0, -1.0, count)
+        d = derived_moduli(mat)
+        mat["nu"] = nu
+        mat["kappa"] = d["rho"] * nu * dt / (d["D"] * z)
+        A, B, C, E = jacobians(mat)
+        star = star_matrices(A, B, C, v)
+        mat["target_z"] = z
     return dict(mat=mat, star=star, E=E, Q0=Q0, cfl=cfl)
 
 
@@ -237,10 +251,16 @@ def _generate(name, seed, kind, N, n, elements=None):
     is given, return only those elements' inputs."""
     nchunks = (n + CHUNK - 1) // CHUNK
     want = None if elements is None else np.asarray(elements)
+    dt_pre = None
+    if kind == "stiffness":
+        # first pass: the global time step from the CFL condition
+        cmin = min(float(_chunk(seed, c, kind, N, min(CHUNK, n - c * CHUNK))["cfl"].min())
+                   for c in range(nchunks))
+        dt_pre = 0.5 / (2 * N + 1) * cmin
     parts, cfl_min = [], np.inf
     for c in range(nchunks):
         count = min(CHUNK, n - c * CHUNK)
-        ch = _chunk(seed, c, kind, N, count)
+        ch = _chunk(seed, c, kind, N, count, dt=dt_pre)
         cfl_min = min(cfl_min, float(ch["cfl"].min()))
         if want is None:
             parts.append(ch)
@@ -268,12 +288,19 @@ CONFIGS = {
     "n6_heterogeneous_262144": dict(seed=2, kind="heterogeneous", N=6, n=262144),
     # FP32 chain + refinement, N=6, 1,048,576 elements, heterogeneous
     "n6_heterogeneous_1048576": dict(seed=3, kind="heterogeneous", N=6, n=1048576),
+    # stiffness sweep, N=5, 524,288 elements: dt |E_uf,uf| from 1e-2 to 1e6
+    "n5_stiffness_524288": dict(seed=5, kind="stiffness", N=5, n=524288),
 }
 
 
 def make_workload(name, elements=None):
     cfg = CONFIGS[name]
     return _generate(name, cfg["seed"], cfg["kind"], cfg["N"], cfg["n"], elements)
+
+
+def stiffness(w: "Workload") -> np.ndarray:
+    """dt |E_uf,uf| of every element of a workload."""
+    return w.dt * np.abs(w.E[:, UF, UF])
 
 
 def make_small(N, n, seed=0, kind="heterogeneous"):

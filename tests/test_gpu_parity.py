@@ -160,3 +160,69 @@ def test_kernels_agree_with_each_other():
     Qa, _ = _run(w, **KERNELS["reference"])
     Qb, _ = _run(w, **KERNELS["fused_fp64"])
     assert rel_l2(Qb, Qa).max() <= TOL
+
+
+def test_fp32_refinement_progression():
+    """Float32 chain alone, then each float64-residual refinement step,
+    against the oracle on N=6 elements of the heterogeneous distribution."""
+    _say("[gpu] fp32 refinement progression N=6")
+    w = wl.make_small(6, 10, seed=31)
+    Xo, Io = _oracle(w, list(range(w.n)))
+    errs = []
+    for k in range(0, 4):
+        Q, Qi = _run(w, precision="fp32_refine", refine_steps=k)
+        errs.append(float(rel_l2(Q, Xo).max()))
+        assert rel_l2(Qi, Io).max() <= max(10 * errs[-1], TOL)
+    _say(f"  max rel L2 after 0..3 refinement steps: {['%.2e' % e for e in errs]}")
+    assert errs[0] <= 1e-4                 # float32 chain alone
+    assert errs[1] <= TOL and errs[2] <= TOL and errs[3] <= TOL
+    assert errs[1] < errs[0] * 1e-3
+
+
+def test_stiffness_sweep_per_decade():
+    """dt |E_uf,uf| from 1e-2 to 1e6 (N=5): float64 and float32 + refinement
+    within the bar in every stiffness decade."""
+    _say("[gpu] stiffness sweep N=5")
+    w = wl.make_small(5, 48, seed=41, kind="stiffness")
+    z = wl.stiffness(w)
+    dec = np.floor(np.log10(z)).astype(int)
+    pick = []
+    for d in range(-2, 6):
+        pick += list(np.where(dec == d)[0][:2])
+    Xo, _ = ostp.solve(5, w.star[pick], w.E[pick], w.Q0[pick], w.dt)
+    for kw in (dict(precision="fp64"), dict(precision="fp32_refine", refine_steps=1),
+               dict(precision="fp32_refine", refine_steps=2)):
+        Q, _ = _run(w, **kw)
+        err = rel_l2(Q[pick], Xo)
+        per = {int(d): float(err[np.array(dec[pick]) == d].max()) for d in sorted(set(dec[pick]))}
+        _say(f"  {kw}: max rel L2 per decade {per}")
+        assert err.max() <= TOL
+
+
+def _full_size(name, kw, nsample):
+    w = wl.make_workload(name)
+    ids = wl.oracle_sample(w.n)[:nsample]
+    _say(f"  generated {name} n={w.n}; sampled elements {ids}")
+    Q, Qi = api.predict(_dev(w.Q0), _dev(w.star), _dev(w.E), w.dt, w.N, **kw)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Q).all()) and bool(torch.isfinite(Qi).all())
+    Qs, Is = Q[ids].cpu().numpy(), Qi[ids].cpu().numpy()
+    del Q, Qi
+    torch.cuda.empty_cache()
+    Xo, Io = ostp.solve(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
+    err, erri = rel_l2(Qs, Xo), rel_l2(Is, Io)
+    _say(f"  max rel L2 Q {err.max():.3e} Qint {erri.max():.3e}")
+    assert err.max() <= TOL and erri.max() <= TOL
+
+
+def test_full_size_n6_262144_fp64_sampled():
+    """The benchmark's workload and launch: all 262,144 N=6 elements in one
+    call, sampled elements checked against the oracle, all outputs finite."""
+    _say("[gpu] full size n6_heterogeneous_262144 fp64")
+    _full_size("n6_heterogeneous_262144", dict(precision="fp64"), 4)
+
+
+def test_full_size_n6_1048576_fp32_refine_sampled():
+    """1,048,576 N=6 elements through the float32 chain + one refinement step."""
+    _say("[gpu] full size n6_heterogeneous_1048576 fp32_refine")
+    _full_size("n6_heterogeneous_1048576", dict(precision="fp32_refine", refine_steps=1), 2)
