@@ -114,6 +114,22 @@ def time_path(torch, api, dev, w, steps, warmup, **kw):
                 wall_s=wall), Q, Qi
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the float64 fused kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE of one dispatch, each scaled by
+    the ratio measured on a plain device copy), or None if the summary is
+    missing or was taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_fused_fp64_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2108_10565_amd", "csrc", "kernel_fused.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_fused_sha256"):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def rel_l2(X, Xo):
     ax = tuple(range(1, X.ndim))
     return np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))
@@ -126,10 +142,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n6_heterogeneous_262144")
     ap.add_argument("--refine-steps", type=int, default=1)
-    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(8, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (reads and writes BYTES each), "
+                         "to calibrate the FETCH_SIZE / WRITE_SIZE counters, and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "calls": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the predictor is element-local and this build runs on a "
               f"single MI355X; --gpus {args.gpus} is not supported (shard elements across GPUs "
@@ -146,7 +175,7 @@ def main():
     oracle = {}
     if not args.no_cpu_baseline:
         ncores = len(os.sched_getaffinity(0))
-        procs = args.cpu_procs or max(1, min(16, ncores))
+        procs = args.cpu_procs or max(1, min(8, ncores))
         ids = sample[:procs] if len(sample) >= procs else sample
         log(f"[bench] cpu baseline: oracle on {len(ids)} elements, {procs} processes x 1 BLAS thread")
         res, wall = cpu_baseline(w, ids, procs)
@@ -207,6 +236,7 @@ def main():
     p = paths["fp64"]
     kernel_s = p["call_ms_mean"] * 1e-3
     achieved = F_alg * w.n / kernel_s / 1e12
+    traffic = measured_traffic(w.name)
     out = {
         "metric": "element predictor updates/s at N=6 (FP64 vs FP32+refine @ rel L2<=1e-10), % roofline",
         "value": p["el_per_s"],
@@ -223,7 +253,7 @@ def main():
         "config": {"workload": w.name, "degree": w.N, "elements": w.n,
                    "unknowns_per_element": 13 * wl.n_modes(w.N) * (w.N + 1), "dt": w.dt},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
                      "flop_per_element": F_alg,
                      "hbm_gbs": bytes_el * w.n / kernel_s / 1e9,
                      "hbm_frac": bytes_el * w.n / kernel_s / 1e9 / PEAK_HBM_GBS,
