@@ -54,7 +54,7 @@ def test_argument_validation_without_device():
     assert _predict_raw(h, refine=-1) == -1
     assert _predict_raw(h, flags=8) == -1
     assert _predict_raw(h, prec=1, flags=1) == -1       # reference kernel is fp64 only
-    assert "refine" in h.lib.stp_last_error(h.ptr).decode() or True
+    assert h.lib.stp_last_error(h.ptr).decode() != ""
     assert _predict_raw(h, ptr=0) == -1                 # NULL arrays with n > 0
     assert _predict_raw(h, n=0, ptr=0) == 0             # empty call: no-op
     assert h.lib.stp_predict(None, None, 3, 1, 1e-3, None, None, None, None, None, 0, 1, None, 0, 0) == -1
