@@ -4,7 +4,7 @@
 //
 // Mapping.  One lane per column (element e, quantity p, time mode u) of the
 // element's right-hand side b_pmu (eq:b_pmu); 13 (N+1) lanes per element,
-// kElems elements per 512-lane workgroup.  Every lane keeps b[m] for all
+// kElems elements per 512-lane workgroup, lanes ordered quantity-major.  Every lane keeps b[m] for all
 // modes m below the top degree block in registers.  The green-block update
 //     b[p, n, u] -= sum_j Khat^j[n, m] (A^{j*} X[:, m, u])_p ,  n < block_start(g)
 // is lane-local once the star product y_j = (A^{j*} X[:, m, u])_p is known,
@@ -16,21 +16,25 @@
 // Per chunk of up to kChunkMax modes m of degree block g (g = N .. 0):
 //   1. every lane writes b[m] to LDS (top block: b = Q0 (S^-1 w), eq:b_pmu);
 //   2. dark-blue blocks and G coupling: lane (e, p, s) forms X[p, m, s] =
-//      row s of (Z - E*_pp I)^-1 times b[p, m, :] (float64).  A quantity o
+//      row s of (Z - E*_pp I)^-1 times b[p, m, :] (float64).  For E*_pp = 0
+//      that row is a row of Z^-1, which has two non-zeros (Z^-1 is
+//      tridiagonal up to its corner entries: the Legendre integration
+//      recurrence), so such lanes read two entries of b instead of T.  A quantity o
 //      whose row of the strict upper part G of E* holds one coupling G_op to
 //      an uncoupled quantity p (the poroelastic u <- uf, v <- vf, w <- wf)
 //      uses the closed form X_o = Zinv_o (b_o + G_op X_p)
 //      = zr . b_o + dr . b_p with dr = G_op (row of Zinv_o) Zinv_p, so no
 //      extra round is needed; any other upper-triangular E is handled level
 //      by level (level = longest coupling chain below a quantity);
-//   3. green blocks: every lane reads X[q, m, u] of the quantities in its
+//   3. X of the chunk goes from LDS to Q (and dt X[:, :, 0] to Qint) in
+//      contiguous runs, with streaming stores issued before step 4;
+//   4. green blocks: every lane reads X[q, m, u] of the quantities in its
 //      star row, forms y_1..y_3 with its row of A^{1*}, A^{2*}, A^{3*}, and
-//      subtracts Khat^j[n, m] y_j from its registers b[n];
-//   X of the chunk goes to Q (and dt X[:, :, 0] to Qint) from step 2 (or
-//   after the last level for a general E).
+//      subtracts Khat^j[n, m] y_j from its registers b[n].
 // A^{j*} = dt A^j and E* = dt E are formed in-kernel, so every product runs
 // with unit scaling (the paper's libxsmm alpha = 1 remark, section "Roofline
 // model").
+#include <type_traits>
 #include <utility>
 
 #include "common.hpp"
@@ -82,11 +86,15 @@ struct Cfg {
   static constexpr int kSlots = kElems + 1;        // + one dummy slot for spare lanes
   static constexpr int kChunk = kChunkMax < DN ? kChunkMax : DN;
   // Stride (doubles) of one (element, quantity) block of the chunk buffers,
-  // padded so that S = T (mod 16): the LDS address of lane (e, p, u) is then
-  // congruent to its lane index modulo 16 doubles (32 banks of 4 bytes), so
-  // the column-wise accesses of 16 consecutive lanes hit distinct banks.
+  // padded so that S = T (mod 16): with the quantity-major block order the
+  // LDS address of lane (e, p, u) is then congruent to its lane index modulo
+  // 16 doubles (32 banks of 4 bytes), so the column-wise accesses of 16
+  // consecutive lanes hit distinct banks.
   static constexpr int kChunkT = kChunk * T;
   static constexpr int S = kChunkT + (((T - kChunkT) % 16) + 16) % 16;
+  // Offset of the (element slot e, quantity q) block: quantity-major, so the
+  // lanes of one quantity (consecutive e, u) address consecutive runs of T.
+  static __device__ __forceinline__ int blk(int e, int q) { return (q * kSlots + e) * S; }
 };
 
 // Degree block g is processed in nchunks(g) chunks of near-equal size.
@@ -99,6 +107,30 @@ __host__ __device__ constexpr int chunk_start(int g, int cmax, int i) {
          (i < block_size(g) % nchunks(g, cmax) ? i : block_size(g) % nchunks(g, cmax));
 }
 
+// Lane tid -> (element slot es, quantity p, time mode u), quantity-major:
+// the lanes of one quantity are contiguous (kElems * T of them), so the few
+// quantities that take the dense dark-blue path (a non-zero diagonal source
+// term, or a coupling) occupy few waves and the other waves skip it.  Spare
+// lanes past kElems * kCols go to the dummy slot kElems.
+template <int N>
+struct LaneId {
+  int es, p, u;
+  __device__ __forceinline__ explicit LaneId(int tid) {
+    using C = Cfg<N>;
+    constexpr int per_q = C::kElems * C::T;
+    if (tid < C::kElems * C::kCols) {
+      p = tid / per_q;
+      es = (tid % per_q) / C::T;
+      u = tid % C::T;
+    } else {
+      const int i = tid - C::kElems * C::kCols;
+      es = C::kElems;
+      p = (i / C::T) % kNQ;
+      u = i % C::T;
+    }
+  }
+};
+
 template <int N, typename R>
 struct Shared {
   using C = Cfg<N>;
@@ -110,7 +142,7 @@ struct Shared {
   union {
     double A[C::kSlots][3][kNQ][kNQ];       // setup only: A^{j*} = dt A^j
     struct {
-      R bufB[C::kSlots * kNQ * C::S];       // b of the chunk: [e][p] blocks of [chunk][T], stride S
+      R bufB[C::kSlots * kNQ * C::S];       // b of the chunk: [p][e] blocks of [chunk][T], stride S
       R bufX[C::kSlots * kNQ * C::S];       // X of the chunk, same layout
     } c;
   } u;
@@ -342,7 +374,7 @@ struct LaneSetup {
               sa0[k] = static_cast<R>(v0);
               sa1[k] = static_cast<R>(v1);
               sa2[k] = static_cast<R>(v2);
-              sq[k] = (es * kNQ + q) * C::S + u;
+              sq[k] = C::blk(es, q) + u;
             }
           ++cnt;
         }
@@ -414,7 +446,7 @@ struct LaneSetup {
       const double* st = a.star + (active ? e0 + es : 0) * (3 * kNQ * kNQ) + p * kNQ;
 #pragma unroll
       for (int q = 0; q < kNQ; ++q) {
-        const R xq = xs[(es * kNQ + q) * C::S + u];
+        const R xq = xs[C::blk(es, q) + u];
         y0 = fma(static_cast<R>(a.dt * st[q]), xq, y0);
         y1 = fma(static_cast<R>(a.dt * st[kNQ * kNQ + q]), xq, y1);
         y2 = fma(static_cast<R>(a.dt * st[2 * kNQ * kNQ + q]), xq, y2);
@@ -437,13 +469,10 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
   const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
   const int nloc = static_cast<int>(nloc64);
-  // spare lanes past kElems * kCols share the dummy slot kElems (their
-  // values are never stored to memory)
-  const int es = (tid / C::kCols) < kE ? (tid / C::kCols) : kE;
-  const int col = tid % C::kCols;
-  const int p = col / T, u = col % T;
+  const LaneId<N> lid(tid);
+  const int es = lid.es, p = lid.p, u = lid.u;
   const bool active = es < nloc;
-  const int cb = (es * kNQ + p) * C::S;  // this lane's (element, quantity) block in bufB / bufX
+  const int cb = C::blk(es, p);  // this lane's (element, quantity) block in bufB / bufX
   const R* kv = khat_sparse<N, R>();
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);  // (element, quantity) row of this lane
@@ -463,7 +492,16 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   }
   LaneSetup<N, R> L;
   L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
-  const int pb = (es * kNQ + L.gp) * C::S;  // block of the coupled quantity (own block if uncoupled)
+  const int pb = C::blk(es, L.gp);  // block of the coupled quantity (own block if uncoupled)
+  // Quantities without a diagonal source (E*_pp = 0) solve with Z^-1, whose
+  // rows have two non-zeros (columns zc0, zc1 of row u); the dense row u of
+  // (Z - E*_pp I)^-1 and the closure row dr are read only by waves holding a
+  // lane that needs them (wave-uniform flags, scalar branches).
+  using ZS = stp_gen::ZinvSparse<N>;
+  const int cz0 = cb + ZS::col[2 * u], cz1 = cb + ZS::col[2 * u + 1];
+  const double zv0 = ZS::val[2 * u], zv1 = ZS::val[2 * u + 1];
+  const bool wave_stiff = __builtin_amdgcn_ballot_w64(sh.G[es][p][p] != 0.0) != 0;
+  const bool wave_coupled = __builtin_amdgcn_ballot_w64(L.gcount == 1) != 0;
 
   static_for<0, N + 1>([&](auto gi) __attribute__((always_inline)) {
     constexpr int g = N - decltype(gi)::value;
@@ -490,7 +528,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
             if (ee < nloc) {
 #pragma unroll
               for (int uu = 0; uu < T; ++uu)
-                bufB[(ee * kNQ + pp) * C::S + kk * T + uu] = static_cast<R>(q[k] * sinv_w(uu));
+                bufB[C::blk(ee, pp) + kk * T + uu] = static_cast<R>(q[k] * sinv_w(uu));
             }
           }
         } else {
@@ -498,7 +536,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
           for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
             const int ee = i / (kNQ * per), rem = i % (kNQ * per);
             const int pp = rem / per, r = rem % per;
-            bufB[(ee * kNQ + pp) * C::S + r] = static_cast<R>(rin[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + r]);
+            bufB[C::blk(ee, pp) + r] = static_cast<R>(rin[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + r]);
           }
         }
       } else {
@@ -508,35 +546,54 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
       }
       __syncthreads();
       // 2. dark-blue blocks and G coupling (float64)
-      double zr[T];
-#pragma unroll
-      for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
-      constexpr bool direct_store = (Mode == kInit);
       if (L.closure) {
-        // X of this lane; in kInit mode stored to memory right away (runs of
-        // T doubles per (element, quantity) and mode)
-        double* Qd = a.Q + erow * (B * T) + m0 * T + u;
-        double* Id = a.Qint ? a.Qint + erow * B + m0 : nullptr;
-        // every lane reads its own and its coupled quantity's column (its
-        // own again, with dr = 0, when uncoupled): no divergent branch
-        double drr[T];
+        // One straight-line variant per combination of the wave-uniform
+        // flags, so that the LDS reads of all modes of the chunk can be in
+        // flight together.
+        auto dark_blue = [&](auto stiff_c, auto coupled_c) __attribute__((always_inline)) {
+          constexpr bool kStiff = decltype(stiff_c)::value, kCoupled = decltype(coupled_c)::value;
+          double zr[T], drr[T];
+          if constexpr (kStiff) {
 #pragma unroll
-        for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
-        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
-          constexpr int kk = decltype(k)::value;
-          double x = 0.0;
+            for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
+          }
+          if constexpr (kCoupled) {
 #pragma unroll
-          for (int v = 0; v < T; ++v) {
-            x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
-            x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
+            for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
           }
-          bufX[cb + kk * T + u] = static_cast<R>(x);
-          if constexpr (direct_store) {
-            if (active) Qd[kk * T] = x;
-            if (active && Id && u == 0) Id[kk] = a.dt * x;
-          }
-        });
+          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+            constexpr int kk = decltype(k)::value;
+            double x;
+            if constexpr (kStiff) {
+              // dense row u of (Z - E*_pp I)^-1 (Z^-1 for the lanes without
+              // a diagonal source in this wave)
+              x = 0.0;
+#pragma unroll
+              for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+            } else {
+              x = fma(zv0, static_cast<double>(bufB[cz0 + kk * T]), zv1 * static_cast<double>(bufB[cz1 + kk * T]));
+            }
+            if constexpr (kCoupled) {
+              // closure coupling dr . b_p (dr = 0 in uncoupled lanes)
+#pragma unroll
+              for (int v = 0; v < T; ++v) x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
+            }
+            bufX[cb + kk * T + u] = static_cast<R>(x);
+          });
+        };
+        using yes = std::true_type;
+        using no = std::false_type;
+        if (wave_stiff) {
+          if (wave_coupled) dark_blue(yes{}, yes{});
+          else dark_blue(yes{}, no{});
+        } else {
+          if (wave_coupled) dark_blue(no{}, yes{});
+          else dark_blue(no{}, no{});
+        }
       } else {
+        double zr[T];
+#pragma unroll
+        for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
           double x = 0.0;
@@ -557,7 +614,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
               for (int q = p + 1; q < kNQ; ++q) {
                 const double gq = sh.G[es][p][q];
                 if (gq != 0.0) {
-                  const int qb = (es * kNQ + q) * C::S + kk * T;
+                  const int qb = C::blk(es, q) + kk * T;
 #pragma unroll
                   for (int v = 0; v < T; ++v) acc[v] = fma(gq, static_cast<double>(bufX[qb + v]), acc[v]);
                 }
@@ -571,7 +628,52 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
         }
       }
       __syncthreads();
-      // 3. green blocks (lane-local): star product, then Khat columns
+      // 3. outputs of the chunk from the X buffer: every (element, quantity)
+      //    row of the chunk is one contiguous run of c*T doubles of Q, so
+      //    consecutive lanes store consecutive doubles.  Each lane stores
+      //    kOut values in nOut groups of kOutGroup (LDS reads, and for
+      //    kCorrect the loads of Q, issued before the stores) in a rolled
+      //    loop, which keeps the registers of this step few.  The streaming
+      //    stores are issued before the green update, so they drain while it
+      //    computes.  Q <- X (kInit) or Q <- Q + X (kCorrect);
+      //    Qint = dt X[:, :, 0].
+      {
+        constexpr int per = c * T;
+        constexpr int kOutGroup = 3;
+        constexpr int kOut = (kE * kNQ * per + kThreads - 1) / kThreads;
+        constexpr int nOut = (kOut + kOutGroup - 1) / kOutGroup;
+        const int limit = nloc * kNQ * per;
+        double* Qg = a.Q + e0 * (kNQ * B * T);
+        double* Ig = a.Qint ? a.Qint + e0 * (kNQ * B) : nullptr;
+#pragma unroll 1
+        for (int gi = 0; gi < nOut; ++gi) {
+          double xv[kOutGroup], qv[kOutGroup];
+#pragma unroll
+          for (int k = 0; k < kOutGroup; ++k) {
+            const int i = tid + (gi * kOutGroup + k) * kThreads;
+            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
+            const int pp = rem / per, r = rem % per;
+            xv[k] = static_cast<double>(bufX[C::blk(ee < kE ? ee : kE, pp) + r]);
+            if constexpr (Mode == kCorrect)
+              qv[k] = i < limit ? Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kOutGroup; ++k) {
+            const int i = tid + (gi * kOutGroup + k) * kThreads;
+            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
+            const int pp = rem / per, r = rem % per;
+            if (i < limit) {
+              double x = xv[k];
+              if constexpr (Mode == kCorrect) x += qv[k];
+              // streaming stores: Q is written once and not read again here,
+              // so it should not displace the Khat lines in L2
+              __builtin_nontemporal_store(x, &Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r]);
+              if (Ig && r % T == 0) __builtin_nontemporal_store(a.dt * x, &Ig[(ee * kNQ + pp) * B + m0 + r / T]);
+            }
+          }
+        }
+      }
+      // 4. green blocks (lane-local): star product, then Khat columns
       if constexpr (g > 0) {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
@@ -581,22 +683,6 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
           // keep the scheduler from hoisting the next mode's LDS reads
           __builtin_amdgcn_sched_barrier(0);
         });
-      }
-      // 4. outputs not stored in step 2 (kCorrect, general E): coalesced runs
-      //    of c*T; Q <- X (kInit) or Q <- Q + X (kCorrect)
-      if (!(direct_store && L.closure)) {
-        double* Qg = a.Q + e0 * (kNQ * B * T);
-        double* Ig = a.Qint ? a.Qint + e0 * (kNQ * B) : nullptr;
-        constexpr int per = c * T;
-        for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
-          const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-          const int pp = rem / per, r = rem % per;
-          double* q = &Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r];
-          double x = static_cast<double>(bufX[(ee * kNQ + pp) * C::S + r]);
-          if constexpr (Mode == kCorrect) x += *q;
-          *q = x;
-          if (Ig && r % T == 0) Ig[(ee * kNQ + pp) * B + m0 + r / T] = a.dt * x;
-        }
       }
     });
   });
@@ -622,11 +708,10 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
   const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
   const int nloc = static_cast<int>(nloc64);
-  const int es = (tid / C::kCols) < kE ? (tid / C::kCols) : kE;
-  const int col = tid % C::kCols;
-  const int p = col / T, u = col % T;
+  const LaneId<N> lid(tid);
+  const int es = lid.es, p = lid.p, u = lid.u;
   const bool active = es < nloc;
-  const int cb = (es * kNQ + p) * C::S;
+  const int cb = C::blk(es, p);
   const R* kv = khat_sparse<N, R>();
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);
@@ -642,7 +727,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
   L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
   const double zpp = sh.G[es][p][p];
   const bool general_g = __builtin_amdgcn_readfirstlane(__syncthreads_or(active && L.gcount > 1)) != 0;
-  const int pb = (es * kNQ + L.gp) * C::S;
+  const int pb = C::blk(es, L.gp);
   double zrow[T];  // row u of Z
 #pragma unroll
   for (int v = 0; v < T; ++v) zrow[v] = z_entry(u, v);
@@ -659,12 +744,12 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
         for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
           const int ee = i / (kNQ * per), rem = i % (kNQ * per);
           const int pp = rem / per, rr = rem % per;
-          bufX[(ee * kNQ + pp) * C::S + rr] = a.Q[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + rr];
+          bufX[C::blk(ee, pp) + rr] = a.Q[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + rr];
         }
         if constexpr (g == N) {
           for (int i = tid; i < nloc * kNQ * c; i += kThreads) {
             const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
-            bufB[(ee * kNQ + pp) * C::S + kk] = a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk];
+            bufB[C::blk(ee, pp) + kk] = a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk];
           }
         }
       }
@@ -685,11 +770,11 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
         } else {
           for (int q = p + 1; q < kNQ; ++q) {
             const double gq = sh.G[es][p][q];
-            if (gq != 0.0) ex = fma(gq, bufX[(es * kNQ + q) * C::S + kk * T + u], ex);
+            if (gq != 0.0) ex = fma(gq, bufX[C::blk(es, q) + kk * T + u], ex);
           }
         }
         const double res = base - zx + ex;
-        if (active) rout[erow * (B * T) + m * T + u] = static_cast<float>(res);
+        if (active) __builtin_nontemporal_store(static_cast<float>(res), &rout[erow * (B * T) + m * T + u]);
       });
       // Khat term into the rows of lower blocks
       if constexpr (g > 0) {
