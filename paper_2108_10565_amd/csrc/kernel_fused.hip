@@ -635,8 +635,9 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
       //    kCorrect the loads of Q, issued before the stores) in a rolled
       //    loop, which keeps the registers of this step few.  The streaming
       //    stores are issued before the green update, so they drain while it
-      //    computes.  Q <- X (kInit) or Q <- Q + X (kCorrect);
-      //    Qint = dt X[:, :, 0].
+      //    computes.  Q <- X (kInit) or Q <- Q + X (kCorrect); then
+      //    Qint = dt X[:, :, 0] in its own pass (consecutive lanes, consecutive
+      //    modes), so no store instruction runs with one lane in T.
       {
         constexpr int per = c * T;
         constexpr int kOutGroup = 3;
@@ -644,7 +645,6 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
         constexpr int nOut = (kOut + kOutGroup - 1) / kOutGroup;
         const int limit = nloc * kNQ * per;
         double* Qg = a.Q + e0 * (kNQ * B * T);
-        double* Ig = a.Qint ? a.Qint + e0 * (kNQ * B) : nullptr;
 #pragma unroll 1
         for (int gi = 0; gi < nOut; ++gi) {
           double xv[kOutGroup], qv[kOutGroup];
@@ -668,8 +668,24 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
               // streaming stores: Q is written once and not read again here,
               // so it should not displace the Khat lines in L2
               __builtin_nontemporal_store(x, &Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r]);
-              if (Ig && r % T == 0) __builtin_nontemporal_store(a.dt * x, &Ig[(ee * kNQ + pp) * B + m0 + r / T]);
             }
+          }
+        }
+        // Qint of the chunk: c contiguous values per (element, quantity) row.
+        // kCorrect adds dt X to the previous Qint (read and written by the
+        // same lane; Q itself is being rewritten by other lanes above).
+        if (a.Qint) {
+          double* Ig = a.Qint + e0 * (kNQ * B);
+          constexpr int kInt = (kE * kNQ * c + kThreads - 1) / kThreads;
+          const int ilimit = nloc * kNQ * c;
+#pragma unroll
+          for (int k = 0; k < kInt; ++k) {
+            const int j = tid + k * kThreads;
+            const int row = j / c, kk = j % c;
+            const int ee = row / kNQ, pp = row % kNQ;
+            double v = a.dt * static_cast<double>(bufX[C::blk(ee < kE ? ee : kE, pp) + kk * T]);
+            if constexpr (Mode == kCorrect) v += j < ilimit ? Ig[row * B + m0 + kk] : 0.0;
+            if (j < ilimit) __builtin_nontemporal_store(v, &Ig[row * B + m0 + kk]);
           }
         }
       }

@@ -226,3 +226,61 @@ def test_full_size_n6_1048576_fp32_refine_sampled():
     """1,048,576 N=6 elements through the float32 chain + one refinement step."""
     _say("[gpu] full size n6_heterogeneous_1048576 fp32_refine")
     _full_size("n6_heterogeneous_1048576", dict(precision="fp32_refine", refine_steps=1), 2)
+
+
+def _general_operators(N, n, seed, chain_prob=0.35):
+    """Operators outside the poroelastic structure: dense star matrices
+    (every row couples to all 13 quantities, scaled so that dt A^j is of
+    order one) and a random upper-triangular E whose diagonal spans
+    dt E_pp in [-50, 0] and whose rows hold several couplings, forming
+    dependency chains up to the full depth.  Exercises the dense-star and
+    the level-by-level coupling paths of the fused kernel."""
+    w = wl.make_small(N, n, seed=seed)
+    rng = np.random.default_rng(1000 + seed)
+    star = rng.standard_normal((n, 3, 13, 13)) * (0.3 / w.dt)
+    E = np.zeros((n, 13, 13))
+    iu = np.triu_indices(13, 1)
+    for e in range(n):
+        E[e][np.diag_indices(13)] = -rng.uniform(0.0, 50.0, 13) / w.dt
+        mask = rng.random(len(iu[0])) < chain_prob
+        E[e][iu[0][mask], iu[1][mask]] = rng.uniform(-1.0, 1.0, mask.sum()) / w.dt
+        E[e][np.arange(12), np.arange(1, 13)] = rng.uniform(0.5, 1.0, 12) / w.dt  # full-depth chain
+    return w, star, E
+
+
+_GENERAL_CACHE = {}
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
+@pytest.mark.parametrize("N,n", [(2, 7), (5, 4)])
+def test_general_operators_dense_star_coupling_chains(kernel, N, n):
+    _say(f"[gpu] general operators kernel={kernel} N={N} n={n}")
+    if (N, n) not in _GENERAL_CACHE:
+        w, star, E = _general_operators(N, n, seed=60 + N)
+        _GENERAL_CACHE[(N, n)] = (w, star, E) + tuple(ostp.solve(N, star, E, w.Q0, w.dt))
+    w, star, E, Xo, Io = _GENERAL_CACHE[(N, n)]
+    Q, Qi = api.predict(_dev(w.Q0), _dev(star), _dev(E), w.dt, N, **KERNELS[kernel])
+    torch.cuda.synchronize()
+    err = rel_l2(Q.cpu().numpy(), Xo)
+    _say(f"  max rel L2 {err.max():.3e}")
+    assert err.max() <= TOL
+    assert rel_l2(Qi.cpu().numpy(), Io).max() <= TOL
+
+
+@pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2"])
+def test_one_dense_star_row_in_a_group(kernel):
+    """Poroelastic elements, one of which has a star row with more than six
+    non-zero columns: its whole workgroup takes the dense-star path, the
+    other groups keep the sparse one."""
+    _say(f"[gpu] one dense star row kernel={kernel}")
+    N = 4
+    w = wl.make_small(N, 12, seed=70)
+    star = w.star.copy()
+    rng = np.random.default_rng(71)
+    star[3, :, 0, :] += rng.standard_normal((3, 13)) * np.abs(star[3]).max() * 1e-3
+    Q, _ = api.predict(_dev(w.Q0), _dev(star), _dev(w.E), w.dt, N, **KERNELS[kernel])
+    torch.cuda.synchronize()
+    Xo, _ = ostp.solve(N, star, w.E, w.Q0, w.dt)
+    err = rel_l2(Q.cpu().numpy(), Xo)
+    _say(f"  max rel L2 {err.max():.3e}")
+    assert err.max() <= TOL
