@@ -10,6 +10,12 @@ seeds, uploaded once, and are resident in HBM when the timed region starts.
 Prints one JSON line.  `value` is element-updates/s of the float64 path on
 the N=6 workload of 262,144 heterogeneous poroelastic elements; the float32
 chain + refinement path is timed on the same inputs and reported beside it.
+
+    python bench.py --workload lts_mixed_1048576
+
+times instead one cycle of clustered local time stepping (16 batches: four
+rate-2 clusters x degrees 3..6, 1,048,576 elements) replayed from a captured
+HIP graph.
 """
 from __future__ import annotations
 
@@ -130,6 +136,85 @@ def measured_traffic(workload: str):
     return rec["hbm_bytes_per_launch"]
 
 
+def run_lts(args):
+    """One cycle of clustered local time stepping (several degrees and time
+    steps, each cluster predicted rate^(K-1-k) times) captured once as a HIP
+    graph and replayed: element updates per second over the cycle."""
+    log(f"[bench] generating LTS workload {args.workload}")
+    t = time.perf_counter()
+    batches = wl.make_lts_workload(args.workload)
+    cyc = wl.lts_cycle(batches)
+    log(f"[bench] {len(batches)} batches, {sum(b.n for b in batches)} elements, {len(cyc)} launches per cycle, "
+        f"generated in {time.perf_counter() - t:.1f}s")
+    # oracle on the first element of every batch (before the GPU is touched)
+    oracle = {}
+    if not args.no_cpu_baseline:
+        procs = args.cpu_procs or max(1, min(8, len(os.sched_getaffinity(0))))
+        import multiprocessing as mp
+        jobs = [(b.N, b.star[0], b.E[0], b.Q0[0], b.dt) for b in batches]
+        with mp.get_context("fork").Pool(procs) as pool:
+            res = pool.map(_oracle_one, jobs)
+        oracle = {i: r[0] for i, r in enumerate(res)}
+    import torch
+    from paper_2108_10565_amd import api
+    dev = [dict(degree=b.N, dt=b.dt, Q0=torch.from_numpy(b.Q0).to("cuda"),
+                star=torch.from_numpy(b.star).to("cuda"), E=torch.from_numpy(b.E).to("cuda")) for b in batches]
+    for d in dev:
+        n, N = d["Q0"].shape[0], d["degree"]
+        d["Q"] = torch.empty((n, 13, wl.n_modes(N), N + 1), dtype=torch.float64, device="cuda")
+        d["Qint"] = torch.empty((n, 13, wl.n_modes(N)), dtype=torch.float64, device="cuda")
+    updates = sum(batches[i].n for i in cyc)
+    flops = 0
+    for i in cyc:
+        N = batches[i].N
+        _, _, Kh = api.reference_matrices(N)
+        nnz = sum(int((Kh[:, :wl.n_modes(g - 1), wl.n_modes(g - 1):wl.n_modes(g)] != 0).sum())
+                  for g in range(1, N + 1))
+        flops += algorithmic_flops(N, nnz) * batches[i].n
+    paths = {}
+    for name, kw in (("fp64", dict(precision="fp64", refine_steps=0)),
+                     ("fp32_refine", dict(precision="fp32_refine", refine_steps=args.refine_steps))):
+        if name == "fp32_refine" and args.skip_fp32:
+            continue
+        g = api.Graph([dev[i] for i in cyc], **kw)
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            g.launch()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        err = None
+        if oracle:
+            err = max(float(rel_l2(dev[i]["Q"][:1].cpu().numpy(), oracle[i][None])[0]) for i in oracle)
+        paths[name] = dict(ms_per_cycle=ms, el_per_s=updates / (ms * 1e-3), max_rel_l2=err, **kw)
+        log(f"[bench] LTS {name}: {ms:.3f} ms per cycle, {updates / ms / 1e3:.3f} M el/s, max rel L2 {err}")
+        g.close()
+    p = paths["fp64"]
+    achieved = flops / (p["ms_per_cycle"] * 1e-3) / 1e12
+    out = {
+        "metric": "element predictor updates/s over one clustered-LTS cycle (graph replay), % roofline",
+        "value": p["el_per_s"], "unit": "element updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": p["ms_per_cycle"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded heterogeneous poroelastic materials, random tetrahedra, Q0 ~ N(0,1))",
+        "config": {"workload": args.workload, "batches": len(batches), "launches_per_cycle": len(cyc),
+                   "elements": sum(b.n for b in batches), "updates_per_cycle": updates,
+                   "clusters": {str(k): sum(b.n for b in batches if b.meta["cluster"] == k)
+                                for k in sorted({b.meta["cluster"] for b in batches})},
+                   "degrees": sorted({b.N for b in batches}), "dt0": batches[0].dt},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                     "flop_per_cycle": flops},
+        "cpu_baseline": None,
+        "paths": paths,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def rel_l2(X, Xo):
     ax = tuple(range(1, X.ndim))
     return np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))
@@ -165,6 +250,9 @@ def main():
               f"instead, see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload in wl.LTS_CONFIGS:
+        run_lts(args)
+        return
     log(f"[bench] generating workload {args.workload}")
     t = time.perf_counter()
     w = wl.make_workload(args.workload)

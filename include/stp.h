@@ -149,6 +149,59 @@ stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z,
  * float64 kernel (useful FLOP: dense star matrices, non-zero Khat entries). */
 stp_status stp_flops(int degree, double* paper_bound, double* executed);
 
+/* ---- Several batches in one call, and a replayable graph of them ---------
+ *
+ * Clustered local time stepping (subsection "Temporal discretisation with
+ * ADER"; its gain is measured in subsection "Scaling") updates elements that
+ * need a smaller time step more often: with clusters of time steps
+ * dt_k = r^k dt_0 (rate r), one cycle of the largest step predicts cluster k
+ * r^(K-1-k) times.  A batch is one group of elements sharing one degree and
+ * one time step (one cluster of one degree); a cycle is a list of batches,
+ * a batch possibly repeated.  Arrays of a batch have the layout of
+ * stp_predict. */
+typedef struct stp_batch {
+  int degree;            /* 0..STP_MAX_DEGREE                                  */
+  int64_t n_elements;    /* >= 0                                               */
+  double dt;             /* > 0 and finite                                     */
+  const double* star;    /* [n][3][13][13] device                              */
+  const double* E;       /* [n][13][13]    device                              */
+  const double* Q0;      /* [n][13][B]     device                              */
+  double* Q;             /* [n][13][B][T]  device, out                         */
+  double* Qint;          /* [n][13][B]     device, out, may be NULL            */
+} stp_batch;
+
+/* Workspace for stp_predict_batched / stp_graph_create: the largest
+ * stp_workspace_size of any batch (the batches run one after the other on
+ * one stream and reuse it). */
+stp_status stp_batched_workspace_size(stp_handle handle, int n_batches, const stp_batch* batches,
+                                      stp_precision precision, int refine_steps, size_t* bytes);
+
+/* Predicts batches[0..n_batches-1] in order on `hip_stream`, each exactly as
+ * stp_predict would (same kernels, bitwise the same results).  Every batch is
+ * checked before anything is launched: a bad batch returns its error, with
+ * its index in stp_last_error, and launches nothing.  n_batches == 0 is a
+ * no-op.  Allocates nothing; does not synchronise. */
+stp_status stp_predict_batched(stp_handle handle, void* hip_stream, int n_batches, const stp_batch* batches,
+                               stp_precision precision, int refine_steps, void* workspace,
+                               size_t workspace_bytes, unsigned flags);
+
+/* A HIP graph holding the launches of one stp_predict_batched call, captured
+ * on `hip_stream` (which must not be the NULL stream; nothing runs during
+ * capture).  The graph keeps the device pointers, sizes and time steps of
+ * the batches as they were at capture: replaying it predicts from whatever
+ * the input arrays then hold.  The graph owns host-side HIP objects only;
+ * the caller keeps every array and the workspace alive while it may run.
+ * No memset or allocation is recorded in it.  Destroy with
+ * stp_graph_destroy (after its last launch has completed). */
+typedef struct stp_graph_s* stp_graph;
+stp_status stp_graph_create(stp_handle handle, void* hip_stream, int n_batches, const stp_batch* batches,
+                            stp_precision precision, int refine_steps, void* workspace,
+                            size_t workspace_bytes, unsigned flags, stp_graph* graph);
+/* Launches the graph on `hip_stream` (any stream, NULL included); does not
+ * synchronise. */
+stp_status stp_graph_launch(stp_graph graph, void* hip_stream);
+stp_status stp_graph_destroy(stp_graph graph);
+
 const char* stp_status_string(stp_status status);
 /* Human-readable detail of the last failure on this handle ("" if none). */
 const char* stp_last_error(stp_handle handle);

@@ -21,7 +21,16 @@ STP_FP32_REFINE = 1
 STP_FLAG_REFERENCE_KERNEL = 1
 MAX_DEGREE = 7
 EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "stp_validate",
-            "stp_reference_matrices", "stp_flops", "stp_status_string", "stp_last_error")
+            "stp_reference_matrices", "stp_flops", "stp_batched_workspace_size",
+            "stp_predict_batched", "stp_graph_create", "stp_graph_launch", "stp_graph_destroy",
+            "stp_status_string", "stp_last_error")
+
+
+class StpBatch(ctypes.Structure):
+    """struct stp_batch of include/stp.h."""
+    _fields_ = [("degree", ctypes.c_int), ("n_elements", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("star", ctypes.c_void_p), ("E", ctypes.c_void_p), ("Q0", ctypes.c_void_p),
+                ("Q", ctypes.c_void_p), ("Qint", ctypes.c_void_p)]
 
 _lib = None
 
@@ -52,12 +61,22 @@ def load(path: str = LIB_PATH):
     lib.stp_validate.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp]
     lib.stp_reference_matrices.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.stp_flops.argtypes = [ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    pb = ctypes.POINTER(StpBatch)
+    lib.stp_batched_workspace_size.argtypes = [vp, ctypes.c_int, pb, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(sz)]
+    lib.stp_predict_batched.argtypes = [vp, vp, ctypes.c_int, pb, ctypes.c_int, ctypes.c_int, vp, sz,
+                                        ctypes.c_uint]
+    lib.stp_graph_create.argtypes = [vp, vp, ctypes.c_int, pb, ctypes.c_int, ctypes.c_int, vp, sz,
+                                     ctypes.c_uint, ctypes.POINTER(vp)]
+    lib.stp_graph_launch.argtypes = [vp, vp]
+    lib.stp_graph_destroy.argtypes = [vp]
     lib.stp_status_string.argtypes = [ctypes.c_int]
     lib.stp_status_string.restype = ctypes.c_char_p
     lib.stp_last_error.argtypes = [vp]
     lib.stp_last_error.restype = ctypes.c_char_p
-    for name in EXPORTED[:-2]:
-        getattr(lib, name).restype = ctypes.c_int
+    for name in EXPORTED:
+        if name not in ("stp_status_string", "stp_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 

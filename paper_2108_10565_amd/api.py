@@ -46,12 +46,8 @@ def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine
     is asynchronous on ``stream`` (default: torch's current stream)."""
     import torch
     h = _h()
-    n = int(Q0.shape[0])
+    n = _check_inputs(Q0, star, E, degree)
     B, T = n_modes(degree), degree + 1
-    for name, t, shape in (("Q0", Q0, (n, 13, B)), ("star", star, (n, 3, 13, 13)), ("E", E, (n, 13, 13))):
-        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
-            raise ValueError(f"{name}: expected contiguous cuda float64 {shape}, got "
-                             f"{tuple(t.shape)} {t.dtype} cuda={t.is_cuda}")
     if Q is None:
         Q = torch.empty((n, 13, B, T), dtype=torch.float64, device=Q0.device)
     if Qint is None and with_qint:
@@ -65,6 +61,110 @@ def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine
                               _ptr(star), _ptr(E), _ptr(Q0), _ptr(Q), _ptr(Qint), _PREC[precision],
                               refine_steps, _ptr(work), ws, flags))
     return Q, Qint
+
+
+def _check_inputs(Q0, star, E, degree):
+    import torch
+    n = int(Q0.shape[0])
+    B = n_modes(degree)
+    for name, t, shape in (("Q0", Q0, (n, 13, B)), ("star", star, (n, 3, 13, 13)), ("E", E, (n, 13, 13))):
+        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: expected contiguous cuda float64 {shape}, got "
+                             f"{tuple(t.shape)} {t.dtype} cuda={t.is_cuda}")
+    return n
+
+
+def _batch_array(batches, with_qint=True):
+    """Allocates missing outputs and fills a ctypes stp_batch array.
+
+    ``batches``: list of dicts with keys degree, dt, Q0, star, E and
+    optionally Q, Qint (outputs written in place)."""
+    import torch
+    arr = (_lib.StpBatch * max(len(batches), 1))()
+    for i, b in enumerate(batches):
+        N = int(b["degree"])
+        n = _check_inputs(b["Q0"], b["star"], b["E"], N)
+        if b.get("Q") is None:
+            b["Q"] = torch.empty((n, 13, n_modes(N), N + 1), dtype=torch.float64, device=b["Q0"].device)
+        if b.get("Qint") is None and with_qint:
+            b["Qint"] = torch.empty((n, 13, n_modes(N)), dtype=torch.float64, device=b["Q0"].device)
+        arr[i] = _lib.StpBatch(N, n, float(b["dt"]), b["star"].data_ptr(), b["E"].data_ptr(),
+                               b["Q0"].data_ptr(), b["Q"].data_ptr(),
+                               b["Qint"].data_ptr() if b.get("Qint") is not None else 0)
+    return arr
+
+
+def _batched_workspace(arr, count, precision, refine_steps, device):
+    import torch
+    h = _h()
+    out = ctypes.c_size_t()
+    h.check(h.lib.stp_batched_workspace_size(h.ptr, count, arr, _PREC[precision], refine_steps,
+                                             ctypes.byref(out)))
+    return torch.empty(out.value, dtype=torch.uint8, device=device) if out.value else None
+
+
+def predict_batched(batches, precision: str = "fp64", refine_steps: int = 1, with_qint: bool = True,
+                    reference_kernel: bool = False, stream=None):
+    """stp_predict_batched: every batch (dict with degree, dt, Q0, star, E and
+    optional Q, Qint) predicted in order on one stream; returns the batches
+    with their Q and Qint filled in."""
+    import torch
+    h = _h()
+    if not batches:
+        return batches
+    arr = _batch_array(batches, with_qint)
+    dev = batches[0]["Q0"].device
+    work = _batched_workspace(arr, len(batches), precision, refine_steps, dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    flags = _lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0
+    h.check(h.lib.stp_predict_batched(h.ptr, ctypes.c_void_p(stream.cuda_stream), len(batches), arr,
+                                      _PREC[precision], refine_steps, _ptr(work),
+                                      work.numel() if work is not None else 0, flags))
+    return batches
+
+
+class Graph:
+    """stp_graph_create / stp_graph_launch / stp_graph_destroy: the launches
+    of one stp_predict_batched call captured once on ``capture_stream`` (a
+    non-default torch stream; a new one if None) and replayed by launch().
+    Keeps the batches' tensors and the workspace alive."""
+
+    def __init__(self, batches, precision: str = "fp64", refine_steps: int = 1, with_qint: bool = True,
+                 reference_kernel: bool = False, capture_stream=None):
+        import torch
+        self._h = _h()
+        self.batches = batches
+        self._arr = _batch_array(batches, with_qint)
+        dev = batches[0]["Q0"].device if batches else torch.device("cuda")
+        self._work = _batched_workspace(self._arr, len(batches), precision, refine_steps, dev)
+        self._stream = capture_stream if capture_stream is not None else torch.cuda.Stream(dev)
+        flags = _lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0
+        self.ptr = ctypes.c_void_p()
+        torch.cuda.current_stream(dev).synchronize()
+        self._h.check(self._h.lib.stp_graph_create(
+            self._h.ptr, ctypes.c_void_p(self._stream.cuda_stream), len(batches), self._arr,
+            _PREC[precision], refine_steps, _ptr(self._work),
+            self._work.numel() if self._work is not None else 0, flags, ctypes.byref(self.ptr)))
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        st = self._h.lib.stp_graph_launch(self.ptr, ctypes.c_void_p(stream.cuda_stream))
+        if st != _lib.STP_OK:
+            raise _lib.StpError(st, "stp_graph_launch")
+
+    def close(self):
+        if self.ptr:
+            self._h.lib.stp_graph_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def validate(Q0, star, E, dt: float, degree: int, stream=None) -> None:

@@ -14,6 +14,11 @@ struct stp_handle_s {
   std::string last_error;
 };
 
+struct stp_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 stp_status fail(stp_handle h, stp_status s, const std::string& msg) {
@@ -62,6 +67,67 @@ stp_status check_common(stp_handle h, int degree, int64_t n, double dt) {
   return STP_OK;
 }
 
+// Checks one prediction request (everything that needs no device access).
+stp_status check_predict(stp_handle h, int degree, int64_t n, double dt, const double* star, const double* E,
+                         const double* Q0, double* Q, stp_precision precision, int refine_steps,
+                         const void* workspace, size_t workspace_bytes, unsigned flags) {
+  stp_status st = check_common(h, degree, n, dt);
+  if (st != STP_OK) return st;
+  if (precision != STP_FP64 && precision != STP_FP32_REFINE) return fail(h, STP_EINVAL, "unknown precision");
+  if (refine_steps < 0 || refine_steps > STP_MAX_REFINE)
+    return fail(h, STP_EINVAL, "refine_steps must be in 0..3");
+  if (flags & ~STP_FLAG_REFERENCE_KERNEL) return fail(h, STP_EINVAL, "unknown flags");
+  if ((flags & STP_FLAG_REFERENCE_KERNEL) && precision != STP_FP64)
+    return fail(h, STP_EINVAL, "the reference kernel is float64 only");
+  if (n == 0) return STP_OK;
+  if (!star || !E || !Q0 || !Q) return fail(h, STP_EINVAL, "NULL array pointer");
+  const size_t need = stp::workspace_bytes(degree, n, static_cast<int>(precision), refine_steps);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(h, STP_EWORKSPACE,
+                "workspace of " + std::to_string(need) + " bytes needed, got " + std::to_string(workspace_bytes));
+  return STP_OK;
+}
+
+// Launches one checked prediction request on `stream`.
+stp_status launch_predict(stp_handle h, hipStream_t stream, int degree, int64_t n, double dt, const double* star,
+                          const double* E, const double* Q0, double* Q, double* Qint, stp_precision precision,
+                          int refine_steps, void* workspace, unsigned flags) {
+  if (n == 0) return STP_OK;
+  stp::PredictArgs a{n, dt, star, E, Q0, Q, Qint};
+  hipError_t err;
+  if (flags & STP_FLAG_REFERENCE_KERNEL)
+    err = stp::launch_reference_kernel(degree, a, stream);
+  else
+    err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps,
+                                   static_cast<float*>(workspace), stream);
+  if (err != hipSuccess) return hip_fail(h, err, "kernel launch");
+  return STP_OK;
+}
+
+stp_status check_batches(stp_handle h, int n_batches, const stp_batch* batches, stp_precision precision,
+                         int refine_steps, const void* workspace, size_t workspace_bytes, unsigned flags) {
+  if (n_batches < 0) return fail(h, STP_EINVAL, "n_batches < 0");
+  if (n_batches > 0 && !batches) return fail(h, STP_EINVAL, "NULL batches");
+  for (int i = 0; i < n_batches; ++i) {
+    const stp_batch& b = batches[i];
+    const stp_status st = check_predict(h, b.degree, b.n_elements, b.dt, b.star, b.E, b.Q0, b.Q, precision,
+                                        refine_steps, workspace, workspace_bytes, flags);
+    if (st != STP_OK) return fail(h, st, "batch " + std::to_string(i) + ": " + h->last_error);
+  }
+  return STP_OK;
+}
+
+stp_status launch_batches(stp_handle h, hipStream_t stream, int n_batches, const stp_batch* batches,
+                          stp_precision precision, int refine_steps, void* workspace, unsigned flags) {
+  for (int i = 0; i < n_batches; ++i) {
+    const stp_batch& b = batches[i];
+    const stp_status st = launch_predict(h, stream, b.degree, b.n_elements, b.dt, b.star, b.E, b.Q0, b.Q, b.Qint,
+                                         precision, refine_steps, workspace, flags);
+    if (st != STP_OK) return fail(h, st, "batch " + std::to_string(i) + ": " + h->last_error);
+  }
+  return STP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -93,32 +159,92 @@ stp_status stp_predict(stp_handle handle, void* hip_stream, int degree, int64_t 
                        const double* star, const double* E, const double* Q0, double* Q, double* Qint,
                        stp_precision precision, int refine_steps, void* workspace,
                        size_t workspace_bytes, unsigned flags) {
-  stp_status st = check_common(handle, degree, n_elements, dt);
-  if (st != STP_OK) return st;
+  if (!handle) return STP_EINVAL;
   handle->last_error.clear();
-  if (precision != STP_FP64 && precision != STP_FP32_REFINE)
-    return fail(handle, STP_EINVAL, "unknown precision");
-  if (refine_steps < 0 || refine_steps > STP_MAX_REFINE)
-    return fail(handle, STP_EINVAL, "refine_steps must be in 0..3");
-  if (flags & ~STP_FLAG_REFERENCE_KERNEL) return fail(handle, STP_EINVAL, "unknown flags");
-  if ((flags & STP_FLAG_REFERENCE_KERNEL) && precision != STP_FP64)
-    return fail(handle, STP_EINVAL, "the reference kernel is float64 only");
-  if (n_elements == 0) return STP_OK;
-  if (!star || !E || !Q0 || !Q) return fail(handle, STP_EINVAL, "NULL array pointer");
-  const size_t need = stp::workspace_bytes(degree, n_elements, static_cast<int>(precision), refine_steps);
-  if (need > 0 && (!workspace || workspace_bytes < need))
-    return fail(handle, STP_EWORKSPACE,
-                "workspace of " + std::to_string(need) + " bytes needed, got " + std::to_string(workspace_bytes));
-  stp::PredictArgs a{n_elements, dt, star, E, Q0, Q, Qint};
-  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  hipError_t err;
-  if (flags & STP_FLAG_REFERENCE_KERNEL)
-    err = stp::launch_reference_kernel(degree, a, stream);
-  else
-    err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps,
-                                   static_cast<float*>(workspace), stream);
-  if (err != hipSuccess) return hip_fail(handle, err, "kernel launch");
+  const stp_status st = check_predict(handle, degree, n_elements, dt, star, E, Q0, Q, precision, refine_steps,
+                                      workspace, workspace_bytes, flags);
+  if (st != STP_OK) return st;
+  return launch_predict(handle, static_cast<hipStream_t>(hip_stream), degree, n_elements, dt, star, E, Q0, Q, Qint,
+                        precision, refine_steps, workspace, flags);
+}
+
+stp_status stp_batched_workspace_size(stp_handle handle, int n_batches, const stp_batch* batches,
+                                      stp_precision precision, int refine_steps, size_t* bytes) {
+  if (!handle || !bytes) return STP_EINVAL;
+  if (n_batches < 0 || (n_batches > 0 && !batches)) return fail(handle, STP_EINVAL, "batches");
+  size_t need = 0;
+  for (int i = 0; i < n_batches; ++i) {
+    size_t b = 0;
+    const stp_status st = stp_workspace_size(handle, batches[i].degree, batches[i].n_elements, precision,
+                                             refine_steps, &b);
+    if (st != STP_OK) return fail(handle, st, "batch " + std::to_string(i) + ": " + handle->last_error);
+    need = b > need ? b : need;
+  }
+  *bytes = need;
   return STP_OK;
+}
+
+stp_status stp_predict_batched(stp_handle handle, void* hip_stream, int n_batches, const stp_batch* batches,
+                               stp_precision precision, int refine_steps, void* workspace,
+                               size_t workspace_bytes, unsigned flags) {
+  if (!handle) return STP_EINVAL;
+  handle->last_error.clear();
+  const stp_status st =
+      check_batches(handle, n_batches, batches, precision, refine_steps, workspace, workspace_bytes, flags);
+  if (st != STP_OK) return st;
+  return launch_batches(handle, static_cast<hipStream_t>(hip_stream), n_batches, batches, precision,
+                        refine_steps, workspace, flags);
+}
+
+stp_status stp_graph_create(stp_handle handle, void* hip_stream, int n_batches, const stp_batch* batches,
+                            stp_precision precision, int refine_steps, void* workspace,
+                            size_t workspace_bytes, unsigned flags, stp_graph* graph) {
+  if (!handle || !graph) return STP_EINVAL;
+  *graph = nullptr;
+  handle->last_error.clear();
+  if (!hip_stream) return fail(handle, STP_EINVAL, "graph capture needs a non-NULL stream");
+  stp_status st =
+      check_batches(handle, n_batches, batches, precision, refine_steps, workspace, workspace_bytes, flags);
+  if (st != STP_OK) return st;
+  stp_graph g = new (std::nothrow) stp_graph_s();
+  if (!g) return fail(handle, STP_ENOMEM, "out of host memory");
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t err = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (err != hipSuccess) {
+    delete g;
+    return hip_fail(handle, err, "hipStreamBeginCapture");
+  }
+  st = launch_batches(handle, stream, n_batches, batches, precision, refine_steps, workspace, flags);
+  const std::string launch_error = handle->last_error;
+  err = hipStreamEndCapture(stream, &g->graph);
+  if (st == STP_OK && err != hipSuccess) st = hip_fail(handle, err, "hipStreamEndCapture");
+  if (st == STP_OK) {
+    err = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) st = hip_fail(handle, err, "hipGraphInstantiate");
+  } else if (!launch_error.empty()) {
+    handle->last_error = launch_error;
+  }
+  if (st != STP_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *graph = g;
+  return STP_OK;
+}
+
+stp_status stp_graph_launch(stp_graph graph, void* hip_stream) {
+  if (!graph || !graph->exec) return STP_EINVAL;
+  return hipGraphLaunch(graph->exec, static_cast<hipStream_t>(hip_stream)) == hipSuccess ? STP_OK : STP_EHIP;
+}
+
+stp_status stp_graph_destroy(stp_graph graph) {
+  if (!graph) return STP_EINVAL;
+  hipError_t e1 = graph->exec ? hipGraphExecDestroy(graph->exec) : hipSuccess;
+  hipError_t e2 = graph->graph ? hipGraphDestroy(graph->graph) : hipSuccess;
+  delete graph;
+  return (e1 == hipSuccess && e2 == hipSuccess) ? STP_OK : STP_EHIP;
 }
 
 stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,

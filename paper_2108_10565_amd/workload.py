@@ -298,6 +298,65 @@ def make_workload(name, elements=None):
     return _generate(name, cfg["seed"], cfg["kind"], cfg["N"], cfg["n"], elements)
 
 
+# Clustered local time stepping: shares of the elements per cluster (cluster k
+# steps with dt_k = rate^k dt_0) and the polynomial degrees mixed in each.
+LTS_SHARES = (0.60, 0.25, 0.10, 0.05)
+LTS_DEGREES = (3, 4, 5, 6)
+LTS_CONFIGS = {
+    # 1,048,576 elements in 4 rate-2 clusters x degrees 3..6 (16 batches)
+    "lts_mixed_1048576": dict(seed=4, n=1048576, rate=2),
+}
+
+
+def make_lts(n_total, seed=4, rate=2, shares=LTS_SHARES, degrees=LTS_DEGREES, name="lts"):
+    """Synthetic clustered-LTS workload: a list of batches (Workload objects
+    with ``meta["cluster"]``), one per (cluster k, degree N).
+
+    Cluster k holds ``shares[k]`` of the elements, split evenly over
+    ``degrees``; each batch is a heterogeneous workload of its own seed whose
+    elements are ``rate**k`` times larger (the star matrices, which carry
+    the inverse element size, are scaled by ``rate**-k``).  The time step of
+    cluster k is ``rate**k * dt_0``, with dt_0 the global (most restrictive)
+    step of the CFL condition at the highest degree over all elements before
+    scaling -- so every batch satisfies its CFL condition."""
+    raw, cfl_min = [], np.inf
+    sizes = [int(round(n_total * sh)) for sh in shares]
+    sizes[0] = n_total - sum(sizes[1:])          # the smallest-step cluster takes the rounding
+    for k, nk in enumerate(sizes):
+        per = [nk // len(degrees) + (1 if i < nk % len(degrees) else 0) for i in range(len(degrees))]
+        for i, N in enumerate(degrees):
+            if per[i] == 0:
+                continue
+            w = _generate(f"{name}_k{k}_N{N}", seed * 1000 + 10 * k + i, "heterogeneous", N, per[i])
+            cfl_min = min(cfl_min, w.dt * (2 * N + 1) / 0.5)
+            raw.append((k, w))
+    dt0 = 0.5 / (2 * max(degrees) + 1) * cfl_min
+    out = []
+    for k, w in raw:
+        meta = dict(w.meta, cluster=k, rate=rate)
+        out.append(Workload(name=w.name, N=w.N, n=w.n, dt=dt0 * rate ** k,
+                            star=np.ascontiguousarray(w.star * float(rate) ** -k), E=w.E, Q0=w.Q0, meta=meta))
+    return out
+
+
+def make_lts_workload(name):
+    cfg = LTS_CONFIGS[name]
+    return make_lts(cfg["n"], seed=cfg["seed"], rate=cfg["rate"], name=name)
+
+
+def lts_cycle(batches):
+    """Indices of ``batches`` in the order of one cycle of the largest time
+    step: sub-steps s = 0 .. rate^(K-1) - 1 of dt_0; cluster k is predicted
+    at the start of each of its steps (s a multiple of rate^k), so
+    rate^(K-1-k) times per cycle."""
+    if not batches:
+        return []
+    rate = batches[0].meta["rate"]
+    K = 1 + max(b.meta["cluster"] for b in batches)
+    return [i for s in range(rate ** (K - 1)) for i, b in enumerate(batches)
+            if s % rate ** b.meta["cluster"] == 0]
+
+
 def stiffness(w: "Workload") -> np.ndarray:
     """dt |E_uf,uf| of every element of a workload."""
     return w.dt * np.abs(w.E[:, UF, UF])

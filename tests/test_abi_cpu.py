@@ -102,3 +102,61 @@ def test_executed_flops_n6():
     + dense star 589134 + sparse Khat 2*91*3920."""
     _, ex = api.flops(6)
     assert ex == 7644 + 107016 + 3528 + 589134 + 2 * 91 * 3920
+
+
+def _batches(*specs):
+    arr = (_lib.StpBatch * len(specs))()
+    for i, (deg, n, dt, ptr) in enumerate(specs):
+        arr[i] = _lib.StpBatch(deg, n, dt, ptr, ptr, ptr, ptr, ptr)
+    return arr
+
+
+def test_batched_argument_validation_without_device():
+    h = _lib.Handle()
+    lib = h.lib
+    ok = (3, 1, 1e-3, 1)
+    assert lib.stp_predict_batched(h.ptr, None, 0, None, 0, 1, None, 0, 0) == 0    # nothing to do
+    assert lib.stp_predict_batched(h.ptr, None, -1, None, 0, 1, None, 0, 0) == -1
+    assert lib.stp_predict_batched(h.ptr, None, 2, None, 0, 1, None, 0, 0) == -1
+    arr = _batches(ok, (9, 1, 1e-3, 1))
+    assert lib.stp_predict_batched(h.ptr, None, 2, arr, 0, 1, None, 0, 0) == -2
+    assert "batch 1" in lib.stp_last_error(h.ptr).decode()
+    arr = _batches(ok, ok, (3, 1, -1.0, 1))
+    assert lib.stp_predict_batched(h.ptr, None, 3, arr, 0, 1, None, 0, 0) == -1
+    assert "batch 2" in lib.stp_last_error(h.ptr).decode()
+    arr = _batches((3, 5, 1e-3, 0))                                              # NULL arrays
+    assert lib.stp_predict_batched(h.ptr, None, 1, arr, 0, 1, None, 0, 0) == -1
+    arr = _batches(ok, (6, 4, 1e-3, 1))                                          # no workspace
+    assert lib.stp_predict_batched(h.ptr, None, 2, arr, 1, 1, None, 0, 0) == -7
+    g = ctypes.c_void_p()
+    assert lib.stp_graph_create(h.ptr, None, 1, _batches(ok), 0, 1, None, 0, 0, ctypes.byref(g)) == -1
+    assert "stream" in lib.stp_last_error(h.ptr).decode()
+    assert not g.value
+    assert lib.stp_graph_launch(None, None) == -1
+    assert lib.stp_graph_destroy(None) == -1
+    h.close()
+
+
+def test_batched_workspace_is_the_largest_batch():
+    h = _lib.Handle()
+    specs = [(3, 1000, 1e-3, 1), (6, 10, 1e-3, 1), (5, 300, 1e-3, 1)]
+    out = ctypes.c_size_t()
+    assert h.lib.stp_batched_workspace_size(h.ptr, 3, _batches(*specs), 1, 2, ctypes.byref(out)) == 0
+    expect = max(api.workspace_size(d, n, "fp32_refine", 2) for d, n, _, _ in specs)
+    assert out.value == expect > 0
+    assert h.lib.stp_batched_workspace_size(h.ptr, 3, _batches(*specs), 0, 2, ctypes.byref(out)) == 0
+    assert out.value == 0
+    h.close()
+
+
+def test_lts_cycle_counts_and_time_steps():
+    from paper_2108_10565_amd import workload as wl
+    b = wl.make_lts(120, seed=9)
+    cyc = wl.lts_cycle(b)
+    K = 1 + max(x.meta["cluster"] for x in b)
+    for i, x in enumerate(b):
+        k = x.meta["cluster"]
+        assert cyc.count(i) == 2 ** (K - 1 - k)
+        assert x.dt == b[0].dt * 2 ** k
+    assert sum(x.n for x in b) == 120
+    assert sorted({x.N for x in b}) == [3, 4, 5, 6]

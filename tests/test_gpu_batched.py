@@ -1,0 +1,93 @@
+"""Batched predictions of several (degree, time step) groups in one call, and
+their replay from a captured HIP graph (one cycle of clustered local time
+stepping).  Through the C ABI; expected values from the oracle and from
+single stp_predict calls."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import stp as ostp  # noqa: E402
+from paper_2108_10565_amd import api  # noqa: E402
+from paper_2108_10565_amd import workload as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _batches(ws):
+    return [dict(degree=w.N, dt=w.dt, Q0=_dev(w.Q0), star=_dev(w.star), E=_dev(w.E)) for w in ws]
+
+
+def _rel(X, Xo):
+    return float(np.linalg.norm(X - Xo) / np.linalg.norm(Xo))
+
+
+@pytest.fixture(scope="module")
+def lts_small():
+    return wl.make_lts(120, seed=9)
+
+
+@pytest.mark.parametrize("precision,refine", [("fp64", 0), ("fp32_refine", 2)])
+def test_batched_equals_single_calls_and_oracle(lts_small, precision, refine):
+    _say(f"[gpu] batched LTS {len(lts_small)} batches precision={precision}")
+    bs = api.predict_batched(_batches(lts_small), precision=precision, refine_steps=refine)
+    torch.cuda.synchronize()
+    for w, b in zip(lts_small, bs):
+        Q1, I1 = api.predict(b["Q0"], b["star"], b["E"], w.dt, w.N, precision=precision, refine_steps=refine)
+        torch.cuda.synchronize()
+        assert torch.equal(b["Q"], Q1) and torch.equal(b["Qint"], I1), w.name
+        Xo, Io = ostp.solve(w.N, w.star[:1], w.E[:1], w.Q0[:1], w.dt)
+        err = _rel(b["Q"][0].cpu().numpy(), Xo[0])
+        _say(f"  {w.name} n={w.n} dt={w.dt:.3e} rel L2 {err:.2e}")
+        assert err <= TOL and _rel(b["Qint"][0].cpu().numpy(), Io[0]) <= TOL
+
+
+@pytest.mark.parametrize("precision,refine", [("fp64", 0), ("fp32_refine", 1)])
+def test_graph_of_one_lts_cycle_replays(lts_small, precision, refine):
+    """Capture the cycle (60 launches), replay it several times with eager
+    work and synchronisations in between, and compare every replay with an
+    eager batched call; then double Q0 in place: the replay, reading the new
+    inputs through the captured pointers, must give exactly twice Q."""
+    _say(f"[gpu] graph LTS cycle precision={precision}")
+    cyc = wl.lts_cycle(lts_small)
+    base = _batches(lts_small)
+    eager = api.predict_batched([dict(b) for b in base], precision=precision, refine_steps=refine)
+    torch.cuda.synchronize()
+    batches = [dict(base[i]) for i in cyc]
+    # repeated predictions of a batch share its outputs
+    for j, i in enumerate(cyc):
+        if cyc.index(i) < j:
+            batches[j] = batches[cyc.index(i)]
+        else:
+            batches[j]["Q"] = torch.full_like(eager[i]["Q"], float("nan"))
+            batches[j]["Qint"] = torch.full_like(eager[i]["Qint"], float("nan"))
+    g = api.Graph(batches, precision=precision, refine_steps=refine)
+    scratch = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        for j, i in enumerate(cyc):
+            assert torch.equal(batches[j]["Q"], eager[i]["Q"]), (rep, j)
+            assert torch.equal(batches[j]["Qint"], eager[i]["Qint"]), (rep, j)
+        scratch.mul_(1.0001).add_(1.0)           # eager work between replays
+        torch.cuda.synchronize()
+        _say(f"  replay {rep}: all {len(cyc)} launches equal the eager call")
+    for b in base:
+        b["Q0"].mul_(2.0)
+    g.launch()
+    torch.cuda.synchronize()
+    for j, i in enumerate(cyc):
+        assert torch.equal(batches[j]["Q"], 2.0 * eager[i]["Q"]), j
+    g.close()
