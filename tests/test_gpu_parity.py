@@ -284,3 +284,52 @@ def test_one_dense_star_row_in_a_group(kernel):
     err = rel_l2(Q.cpu().numpy(), Xo)
     _say(f"  max rel L2 {err.max():.3e}")
     assert err.max() <= TOL
+
+
+def test_full_size_n5_stiffness_524288_per_decade():
+    """The stiffness workload at its full size (524,288 N=5 elements,
+    dt |E_uf,uf| from 1e-2 to 1e6): two oracle elements from every decade,
+    float64 and float32 + 1 and 2 refinement steps, all within the bar."""
+    _say("[gpu] full size n5_stiffness_524288 per decade")
+    w = wl.make_workload("n5_stiffness_524288")
+    z = wl.stiffness(w)
+    dec = np.floor(np.log10(z)).astype(int)
+    ids = []
+    for d in range(-2, 6):
+        ids += [int(i) for i in np.where(dec == d)[0][:2]]
+    _say(f"  decades {sorted(set(dec[ids].tolist()))}, elements {ids}")
+    Xo, Io = ostp.solve(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
+    dQ0, dstar, dE = _dev(w.Q0), _dev(w.star), _dev(w.E)
+    for kw in (dict(precision="fp64"), dict(precision="fp32_refine", refine_steps=1),
+               dict(precision="fp32_refine", refine_steps=2)):
+        Q, Qi = api.predict(dQ0, dstar, dE, w.dt, w.N, **kw)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(Q).all())
+        err = rel_l2(Q[ids].cpu().numpy(), Xo)
+        erri = rel_l2(Qi[ids].cpu().numpy(), Io)
+        per = {int(d): float(err[dec[ids] == d].max()) for d in sorted(set(dec[ids].tolist()))}
+        _say(f"  {kw}: max rel L2 per decade {per}")
+        assert err.max() <= TOL and erri.max() <= TOL
+        del Q, Qi
+        torch.cuda.empty_cache()
+
+
+def test_full_size_n6_1048576_refinement_progression():
+    """1,048,576 N=6 elements: the float32 chain alone, then 1, 2 and 3
+    refinement steps, on oracle-checked sampled elements, beside float64."""
+    _say("[gpu] full size n6_heterogeneous_1048576 refinement progression")
+    w = wl.make_workload("n6_heterogeneous_1048576")
+    ids = wl.oracle_sample(w.n)[:3]
+    Xo, _ = ostp.solve(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
+    dQ0, dstar, dE = _dev(w.Q0), _dev(w.star), _dev(w.E)
+    errs = {}
+    for name, kw in (("fp64", dict(precision="fp64")),) + tuple(
+            (f"fp32+{k}", dict(precision="fp32_refine", refine_steps=k)) for k in range(4)):
+        Q, _ = api.predict(dQ0, dstar, dE, w.dt, w.N, with_qint=False, **kw)
+        torch.cuda.synchronize()
+        errs[name] = float(rel_l2(Q[ids].cpu().numpy(), Xo).max())
+        del Q
+        torch.cuda.empty_cache()
+    _say(f"  max rel L2: {errs}")
+    assert errs["fp64"] <= TOL and errs["fp32+0"] <= 1e-4
+    assert all(errs[f"fp32+{k}"] <= TOL for k in (1, 2, 3))
