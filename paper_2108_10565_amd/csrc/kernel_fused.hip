@@ -490,6 +490,19 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(rrow[n * T]);
   }
+  // Q0 of the first chunk (top block): its loads are issued before the
+  // per-element setup so that their latency overlaps it
+  constexpr int kFirstC = chunk_size(N, C::kChunk, 0), kFirstM = chunk_start(N, C::kChunk, 0);
+  constexpr int kFirstPer = (kE * kNQ * kFirstC + kThreads - 1) / kThreads;
+  double q_first[kFirstPer];
+  if constexpr (Mode == kInit) {
+#pragma unroll
+    for (int k = 0; k < kFirstPer; ++k) {
+      const int i = tid + k * kThreads;
+      const int ee = i / (kNQ * kFirstC), pp = (i / kFirstC) % kNQ, kk = i % kFirstC;
+      q_first[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + kFirstM + kk] : 0.0;
+    }
+  }
   LaneSetup<N, R> L;
   L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
   const int pb = C::blk(es, L.gp);  // block of the coupled quantity (own block if uncoupled)
@@ -515,11 +528,17 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
         if constexpr (Mode == kInit) {
           constexpr int per_thread = (kE * kNQ * c + kThreads - 1) / kThreads;
           double q[per_thread];
+          if constexpr (decltype(ci)::value == 0) {
+            static_assert(per_thread == kFirstPer && m0 == kFirstM, "first chunk");
 #pragma unroll
-          for (int k = 0; k < per_thread; ++k) {
-            const int i = tid + k * kThreads;
-            const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
-            q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
+            for (int k = 0; k < per_thread; ++k) q[k] = q_first[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < per_thread; ++k) {
+              const int i = tid + k * kThreads;
+              const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+              q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
+            }
           }
 #pragma unroll
           for (int k = 0; k < per_thread; ++k) {
@@ -711,15 +730,20 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
 //              - sum_j sum_q A^{j*}_pq sum_l Khat^j[n,l] Q[q,l,u],
 // written to `rout` in float (the right-hand side of the correction solve).
 // Same lane mapping and chunk order as the solve; the Khat term is the green
-// update of the solve applied to the known Q, accumulated in float64.
+// update of the solve applied to the known Q, accumulated in float64.  The
+// residual of a chunk is collected in LDS and written in contiguous runs.
 template <int N>
 __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(PredictArgs a, float* rout) {
   using C = Cfg<N>;
   using R = double;
   constexpr int B = C::B, T = C::T, kE = C::kElems, kThreads = C::kThreads;
   __shared__ Shared<N, R> sh;
-  R* const bufB = sh.u.c.bufB;  // Q0 of the chunk (column 0 of each mode's block)
   R* const bufX = sh.u.c.bufX;  // Q of the chunk
+  R* const bufR = sh.u.c.bufB;  // residual of the chunk, same layout, to memory after the chunk
+  // Q0 of a top-block chunk, [element][quantity][mode]; the per-lane rows of
+  // the setup are not used after it
+  double* const q0s = &sh.zr[0][0];
+  static_assert(C::kSlots * kNQ * C::kChunk <= C::kThreads * T, "Q0 staging fits");
   const int tid = threadIdx.x;
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
   const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
@@ -763,10 +787,8 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
           bufX[C::blk(ee, pp) + rr] = a.Q[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + rr];
         }
         if constexpr (g == N) {
-          for (int i = tid; i < nloc * kNQ * c; i += kThreads) {
-            const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
-            bufB[C::blk(ee, pp) + kk] = a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk];
-          }
+          for (int i = tid; i < nloc * kNQ * c; i += kThreads)
+            q0s[i] = a.Q0[(e0 * kNQ + i / c) * B + m0 + i % c];
         }
       }
       __syncthreads();
@@ -775,7 +797,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
         constexpr int kk = decltype(k)::value;
         constexpr int m = m0 + kk;
         double base;
-        if constexpr (g == N) base = bufB[cb + kk] * w;
+        if constexpr (g == N) base = q0s[(es * kNQ + p) * c + kk] * w;
         else base = r[m];
         double zx = 0.0;
 #pragma unroll
@@ -789,8 +811,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
             if (gq != 0.0) ex = fma(gq, bufX[C::blk(es, q) + kk * T + u], ex);
           }
         }
-        const double res = base - zx + ex;
-        if (active) __builtin_nontemporal_store(static_cast<float>(res), &rout[erow * (B * T) + m * T + u]);
+        bufR[cb + kk * T + u] = base - zx + ex;
       });
       // Khat term into the rows of lower blocks
       if constexpr (g > 0) {
@@ -803,6 +824,34 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
         });
       }
       __syncthreads();  // before the next chunk overwrites the buffers
+      // the residual of the chunk to memory: every (element, quantity) row is
+      // one contiguous run of c*T floats (consecutive lanes, consecutive
+      // values), streaming stores; the next chunk writes the residual buffer
+      // only after its own barrier
+      {
+        constexpr int per = c * T;
+        constexpr int kGroupOut = 3;
+        constexpr int iters = (kE * kNQ * per + kThreads - 1) / kThreads;
+        constexpr int ngroups = (iters + kGroupOut - 1) / kGroupOut;
+        const int limit = nloc * kNQ * per;
+        float* const Rg = rout + e0 * (kNQ * B * T) + m0 * T;
+#pragma unroll 1
+        for (int gi = 0; gi < ngroups; ++gi) {
+          float v[kGroupOut];
+#pragma unroll
+          for (int k = 0; k < kGroupOut; ++k) {
+            const int i = tid + (gi * kGroupOut + k) * kThreads;
+            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
+            v[k] = static_cast<float>(bufR[C::blk(ee < kE ? ee : kE, rem / per) + rem % per]);
+          }
+#pragma unroll
+          for (int k = 0; k < kGroupOut; ++k) {
+            const int i = tid + (gi * kGroupOut + k) * kThreads;
+            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
+            if (i < limit) __builtin_nontemporal_store(v[k], &Rg[(ee * kNQ + rem / per) * (B * T) + rem % per]);
+          }
+        }
+      }
     });
   });
 }
