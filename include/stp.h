@@ -202,6 +202,30 @@ stp_status stp_graph_create(stp_handle handle, void* hip_stream, int n_batches, 
 stp_status stp_graph_launch(stp_graph graph, void* hip_stream);
 stp_status stp_graph_destroy(stp_graph graph);
 
+/* ---- Machine ceilings ----------------------------------------------------
+ *
+ * The roofline of subsection "Roofline model" places the predictor against
+ * the peak FLOP/s and memory bandwidth measured on the machine itself.  This
+ * call measures the corresponding ceilings of the GPU: FMA loops on the
+ * vector ALUs (float64, and float32 without packed math, as the kernels are
+ * built) and on the float64 matrix cores, a device-to-device copy and a
+ * write-only stream through HBM.  Each kernel is warmed up, then timed with
+ * HIP events on `hip_stream`; the call synchronises that stream.
+ * `scratch` (device, owned by the caller, contents clobbered) holds the
+ * streams: at least 1 GiB (the two halves are copied into each other) is
+ * needed for a bandwidth reading that caches do not inflate; a smaller buffer
+ * returns STP_EWORKSPACE. */
+typedef struct stp_peaks {
+  double fp64_valu_tflops;   /* v_fma_f64 over all compute units            */
+  double fp32_valu_tflops;   /* v_fma_f32 (no packed float32 instructions)  */
+  double fp64_mfma_tflops;   /* 16x16x4 float64 matrix-core instructions    */
+  double hbm_copy_gbs;       /* bytes read + bytes written per second       */
+  double hbm_write_gbs;      /* bytes written per second                    */
+} stp_peaks;
+
+stp_status stp_measure_peaks(stp_handle handle, void* hip_stream, void* scratch, size_t scratch_bytes,
+                             stp_peaks* peaks);
+
 const char* stp_status_string(stp_status status);
 /* Human-readable detail of the last failure on this handle ("" if none). */
 const char* stp_last_error(stp_handle handle);

@@ -23,7 +23,7 @@ MAX_DEGREE = 7
 EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "stp_validate",
             "stp_reference_matrices", "stp_flops", "stp_batched_workspace_size",
             "stp_predict_batched", "stp_graph_create", "stp_graph_launch", "stp_graph_destroy",
-            "stp_status_string", "stp_last_error")
+            "stp_measure_peaks", "stp_status_string", "stp_last_error")
 
 
 class StpBatch(ctypes.Structure):
@@ -31,6 +31,14 @@ class StpBatch(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int), ("n_elements", ctypes.c_int64), ("dt", ctypes.c_double),
                 ("star", ctypes.c_void_p), ("E", ctypes.c_void_p), ("Q0", ctypes.c_void_p),
                 ("Q", ctypes.c_void_p), ("Qint", ctypes.c_void_p)]
+
+
+class StpPeaks(ctypes.Structure):
+    """struct stp_peaks of include/stp.h."""
+    _fields_ = [("fp64_valu_tflops", ctypes.c_double), ("fp32_valu_tflops", ctypes.c_double),
+                ("fp64_mfma_tflops", ctypes.c_double), ("hbm_copy_gbs", ctypes.c_double),
+                ("hbm_write_gbs", ctypes.c_double)]
+
 
 _lib = None
 
@@ -70,6 +78,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.c_uint, ctypes.POINTER(vp)]
     lib.stp_graph_launch.argtypes = [vp, vp]
     lib.stp_graph_destroy.argtypes = [vp]
+    lib.stp_measure_peaks.argtypes = [vp, vp, vp, sz, ctypes.POINTER(StpPeaks)]
     lib.stp_status_string.argtypes = [ctypes.c_int]
     lib.stp_status_string.restype = ctypes.c_char_p
     lib.stp_last_error.argtypes = [vp]

@@ -167,6 +167,21 @@ class Graph:
             pass
 
 
+def measure_peaks(scratch_bytes: int = 2 << 30, stream=None) -> dict:
+    """stp_measure_peaks: measured FP64/FP32 VALU and FP64 MFMA FMA rates
+    (TFLOP/s) and HBM copy / write bandwidth (GB/s) of the current device."""
+    import torch
+    h = _h()
+    scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = _lib.StpPeaks()
+    h.check(h.lib.stp_measure_peaks(h.ptr, ctypes.c_void_p(stream.cuda_stream), _ptr(scratch), scratch_bytes,
+                                    ctypes.byref(out)))
+    del scratch
+    return {name: getattr(out, name) for name, _ in _lib.StpPeaks._fields_}
+
+
 def validate(Q0, star, E, dt: float, degree: int, stream=None) -> None:
     """Data checks of stp_validate; raises StpError on failure (synchronises)."""
     import torch

@@ -56,7 +56,7 @@ def generate_tables():
 
 def _objects():
     jobs = []
-    for src in ("stp_api.hip", "kernel_ref.hip", "basis.cpp"):
+    for src in ("stp_api.hip", "kernel_ref.hip", "peaks.hip", "basis.cpp"):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         extra = ["-x", "hip"] if src.endswith(".hip") else []
         jobs.append(([HIPCC] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj], obj))

@@ -160,3 +160,12 @@ def test_lts_cycle_counts_and_time_steps():
         assert x.dt == b[0].dt * 2 ** k
     assert sum(x.n for x in b) == 120
     assert sorted({x.N for x in b}) == [3, 4, 5, 6]
+
+
+def test_measure_peaks_argument_checks_without_device():
+    h = _lib.Handle()
+    out = _lib.StpPeaks()
+    assert h.lib.stp_measure_peaks(h.ptr, None, None, 1 << 31, ctypes.byref(out)) == -1
+    assert h.lib.stp_measure_peaks(None, None, ctypes.c_void_p(1), 1 << 31, ctypes.byref(out)) == -1
+    assert h.lib.stp_measure_peaks(h.ptr, None, ctypes.c_void_p(1), 1 << 20, ctypes.byref(out)) == -7
+    h.close()

@@ -91,3 +91,15 @@ def test_graph_of_one_lts_cycle_replays(lts_small, precision, refine):
     for j, i in enumerate(cyc):
         assert torch.equal(batches[j]["Q"], 2.0 * eager[i]["Q"]), j
     g.close()
+
+
+def test_measured_machine_ceilings_are_plausible():
+    """stp_measure_peaks: positive, and below 1.2x the published MI355X
+    figures (FP64 vector and matrix 78.6 TFLOP/s, HBM 8 TB/s), which catches
+    a FLOP or byte count off by a factor."""
+    pk = api.measure_peaks()
+    _say(f"[gpu] measured ceilings {pk}")
+    assert 0 < pk["fp64_valu_tflops"] < 1.2 * 78.6
+    assert 0 < pk["fp32_valu_tflops"] < 1.2 * 157.3
+    assert 0 < pk["fp64_mfma_tflops"] < 1.2 * 78.6
+    assert 0 < pk["hbm_copy_gbs"] < 1.2 * 8000 and 0 < pk["hbm_write_gbs"] < 1.2 * 8000
