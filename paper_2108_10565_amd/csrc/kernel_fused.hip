@@ -303,6 +303,31 @@ __device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y
   }
 }
 
+// Copies columns [m0 T, m0 T + PER) of the (element, quantity) rows of the
+// group (a [n][13][B T] array in memory) into the chunk buffer `buf` (block
+// layout of Cfg::blk), converted to R.  Every lane issues all its loads
+// before its LDS stores, so the group waits for one memory latency, not one
+// per row segment.
+template <int N, typename R, int PER, typename Src>
+__device__ __forceinline__ void stage_rows(R* buf, const Src* src, int64_t e0, int m0T, int nloc, int tid) {
+  using C = Cfg<N>;
+  constexpr int kIters = (C::kElems * kNQ * PER + C::kThreads - 1) / C::kThreads;
+  const int limit = nloc * kNQ * PER;
+  Src v[kIters];
+#pragma unroll
+  for (int k = 0; k < kIters; ++k) {
+    const int i = tid + k * C::kThreads;
+    const int row = i / PER, r = i % PER;
+    v[k] = i < limit ? src[(e0 * kNQ + row) * (C::B * C::T) + m0T + r] : Src(0);
+  }
+#pragma unroll
+  for (int k = 0; k < kIters; ++k) {
+    const int i = tid + k * C::kThreads;
+    const int row = i / PER, r = i % PER;
+    if (i < limit) buf[C::blk(row / kNQ, row % kNQ) + r] = static_cast<R>(v[k]);
+  }
+}
+
 // Modes of the solve kernel.
 constexpr int kInit = 0;     // b = Q0 (S^-1 w); Q <- X
 constexpr int kCorrect = 1;  // b = residual (float workspace); Q <- Q + X
@@ -524,6 +549,18 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
     static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
       constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
       constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
+      constexpr int kOut = (kE * kNQ * c * T + kThreads - 1) / kThreads;  // output values per lane
+      // kCorrect: the previous Q of this lane's output values, loaded at the
+      // start of the chunk so that the latency overlaps steps 1 and 2
+      double qpre[Mode == kCorrect ? kOut : 1];
+      if constexpr (Mode == kCorrect) {
+        constexpr int per = c * T;
+#pragma unroll
+        for (int k = 0; k < kOut; ++k) {
+          const int i = tid + k * kThreads;
+          qpre[k] = i < nloc * kNQ * per ? a.Q[(e0 * kNQ + i / per) * (B * T) + m0 * T + i % per] : 0.0;
+        }
+      }
       if constexpr (g > 0) prefetch_columns<N, R, m0, c, kThreads / 64>(kv, wave);
       // 1. right-hand side of the chunk to LDS; the top block has received no
       //    update yet, so it comes straight from memory
@@ -554,12 +591,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
             }
           }
         } else {
-          constexpr int per = c * T;
-          for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
-            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-            const int pp = rem / per, r = rem % per;
-            bufB[C::blk(ee, pp) + r] = static_cast<R>(rin[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + r]);
-          }
+          stage_rows<N, R, c * T>(bufB, rin, e0, m0 * T, nloc, tid);
         }
       } else {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
@@ -653,9 +685,10 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
       // 3. outputs of the chunk from the X buffer: every (element, quantity)
       //    row of the chunk is one contiguous run of c*T doubles of Q, so
       //    consecutive lanes store consecutive doubles.  Each lane stores
-      //    kOut values in nOut groups of kOutGroup (LDS reads, and for
-      //    kCorrect the loads of Q, issued before the stores) in a rolled
-      //    loop, which keeps the registers of this step few.  The streaming
+      //    kOut values: kInit in nOut groups of kOutGroup (LDS reads issued
+      //    before the stores) in a rolled loop, which keeps the registers of
+      //    this step few; kCorrect adds the previous Q loaded at the start of
+      //    the chunk, in one unrolled pass.  The streaming
       //    stores are issued before the green update, so they drain while it
       //    computes.  Q <- X (kInit) or Q <- Q + X (kCorrect); then
       //    Qint = dt X[:, :, 0] in its own pass (consecutive lanes, consecutive
@@ -663,34 +696,38 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
       {
         constexpr int per = c * T;
         constexpr int kOutGroup = 3;
-        constexpr int kOut = (kE * kNQ * per + kThreads - 1) / kThreads;
         constexpr int nOut = (kOut + kOutGroup - 1) / kOutGroup;
         const int limit = nloc * kNQ * per;
-        double* Qg = a.Q + e0 * (kNQ * B * T);
+        double* Qg = a.Q + e0 * (kNQ * B * T) + m0 * T;
+        // value k of this lane: run index i = tid + k kThreads -> (row, r)
+        auto lds_index = [&](int i) __attribute__((always_inline)) {
+          const int row = i / per;
+          const int ee = row / kNQ;
+          return C::blk(ee < kE ? ee : kE, row % kNQ) + i % per;
+        };
+        // streaming stores: Q is written once and not read again here, so
+        // it should not displace the Khat lines in L2
+        if constexpr (Mode == kInit) {
 #pragma unroll 1
-        for (int gi = 0; gi < nOut; ++gi) {
-          double xv[kOutGroup], qv[kOutGroup];
+          for (int gi = 0; gi < nOut; ++gi) {
+            double xv[kOutGroup];
 #pragma unroll
-          for (int k = 0; k < kOutGroup; ++k) {
-            const int i = tid + (gi * kOutGroup + k) * kThreads;
-            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-            const int pp = rem / per, r = rem % per;
-            xv[k] = static_cast<double>(bufX[C::blk(ee < kE ? ee : kE, pp) + r]);
-            if constexpr (Mode == kCorrect)
-              qv[k] = i < limit ? Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r] : 0.0;
-          }
+            for (int k = 0; k < kOutGroup; ++k)
+              xv[k] = static_cast<double>(bufX[lds_index(tid + (gi * kOutGroup + k) * kThreads)]);
 #pragma unroll
-          for (int k = 0; k < kOutGroup; ++k) {
-            const int i = tid + (gi * kOutGroup + k) * kThreads;
-            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-            const int pp = rem / per, r = rem % per;
-            if (i < limit) {
-              double x = xv[k];
-              if constexpr (Mode == kCorrect) x += qv[k];
-              // streaming stores: Q is written once and not read again here,
-              // so it should not displace the Khat lines in L2
-              __builtin_nontemporal_store(x, &Qg[(ee * kNQ + pp) * (B * T) + m0 * T + r]);
+            for (int k = 0; k < kOutGroup; ++k) {
+              const int i = tid + (gi * kOutGroup + k) * kThreads;
+              if (i < limit) __builtin_nontemporal_store(xv[k], &Qg[(i / per) * (B * T) + i % per]);
             }
+          }
+        } else {
+          double xv[kOut];
+#pragma unroll
+          for (int k = 0; k < kOut; ++k) xv[k] = static_cast<double>(bufX[lds_index(tid + k * kThreads)]);
+#pragma unroll
+          for (int k = 0; k < kOut; ++k) {
+            const int i = tid + k * kThreads;
+            if (i < limit) __builtin_nontemporal_store(xv[k] + qpre[k], &Qg[(i / per) * (B * T) + i % per]);
           }
         }
         // Qint of the chunk: c contiguous values per (element, quantity) row.
@@ -783,12 +820,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
       if constexpr (g > 0) prefetch_columns<N, R, m0, c, kThreads / 64>(kv, wave);
       // stage Q of the chunk (and Q0 of the top block) in LDS, coalesced
       {
-        constexpr int per = c * T;
-        for (int i = tid; i < nloc * kNQ * per; i += kThreads) {
-          const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-          const int pp = rem / per, rr = rem % per;
-          bufX[C::blk(ee, pp) + rr] = a.Q[((e0 + ee) * kNQ + pp) * (B * T) + m0 * T + rr];
-        }
+        stage_rows<N, R, c * T>(bufX, static_cast<const double*>(a.Q), e0, m0 * T, nloc, tid);
         if constexpr (g == N) {
           for (int i = tid; i < nloc * kNQ * c; i += kThreads)
             q0s[i] = a.Q0[(e0 * kNQ + i / c) * B + m0 + i % c];
