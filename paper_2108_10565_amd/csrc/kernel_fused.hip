@@ -4,7 +4,8 @@
 //
 // Mapping.  One lane per column (element e, quantity p, time mode u) of the
 // element's right-hand side b_pmu (eq:b_pmu); 13 (N+1) lanes per element,
-// kElems elements per 512-lane workgroup, lanes ordered quantity-major.
+// kElems elements per workgroup (512 lanes at most), lanes ordered
+// quantity-major.
 // Every lane keeps b[m] for all modes m below the top degree block in
 // registers.  The green-block update
 //     b[p, n, u] -= sum_j Khat^j[n, m] (A^{j*} X[:, m, u])_p ,  n < block_start(g)
@@ -50,9 +51,14 @@
 namespace stp {
 namespace {
 
-constexpr int kMaxThreads = 512;
+// Tile shape per degree: threads per workgroup (upper bound; rounded to
+// whole elements and waves) and modes per chunk (degree blocks are split
+// evenly).  Chosen by a sweep on MI355X at 262,144 elements over {512, 256}
+// threads x {10, 6} modes; 512 x 10 was best or within 3% at N = 4..6, and
+// 256 threads gave 2.5% at N = 3.
+constexpr int kTileThreads[kMaxDegree + 1] = {512, 512, 512, 256, 512, 512, 512, 512};
 constexpr int kMaxElems = 16;
-constexpr int kChunkMax = 10;  // modes per chunk (degree blocks are split evenly)
+constexpr int kChunkMax = 10;
 // Non-zero columns kept per lane of a star-matrix row (union over the three
 // directions).  The poroelastic Jacobians need at most 6 (normal-stress and
 // pressure rows couple to the 6 velocities; velocity rows to 3 stresses and
@@ -83,7 +89,7 @@ struct Cfg {
   static constexpr int DN = block_size(N);         // modes of the top block (largest block)
   static constexpr int kCols = kNQ * T;            // lanes per element
   static constexpr int kElems =                    // elements per workgroup
-      (kMaxThreads / kCols) < kMaxElems ? (kMaxThreads / kCols) : kMaxElems;
+      (kTileThreads[N] / kCols) < kMaxElems ? (kTileThreads[N] / kCols) : kMaxElems;
   static constexpr int kThreads = (kElems * kCols + 63) / 64 * 64;
   static constexpr int kSlots = kElems + 1;        // + one dummy slot for spare lanes
   static constexpr int kChunk = kChunkMax < DN ? kChunkMax : DN;
