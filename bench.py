@@ -245,9 +245,10 @@ def main():
         print(json.dumps({"copy_bytes": n * 8, "calls": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the predictor is element-local and this build runs on a "
-              f"single MI355X; --gpus {args.gpus} is not supported (shard elements across GPUs "
-              f"instead, see DESIGN.md).", file=sys.stderr)
+        print(f"bench.py measures one GPU: the predictor is element-local and runs on a single "
+              f"MI355X; --gpus {args.gpus} is not supported (several GPUs would each predict their "
+              f"own share of the elements, with no communication inside the predictor).",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload in wl.LTS_CONFIGS:
