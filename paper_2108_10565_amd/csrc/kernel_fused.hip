@@ -31,7 +31,8 @@
 //      other upper-triangular E is handled level by level (level = longest
 //      coupling chain below a quantity);
 //   3. X of the chunk goes from LDS to Q (and dt X[:, :, 0] to Qint) in
-//      contiguous runs, with streaming stores issued before step 4;
+//      contiguous runs, with streaming stores issued before and early in
+//      step 4;
 //   4. green blocks: every lane reads X[q, m, u] of the quantities in its
 //      star row, forms y_1..y_3 with its row of A^{1*}, A^{2*}, A^{3*}, and
 //      subtracts Khat^j[n, m] y_j from its registers b[n].
@@ -694,15 +695,20 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
       //    kOut values: kInit in nOut groups of kOutGroup (LDS reads issued
       //    before the stores) in a rolled loop, which keeps the registers of
       //    this step few; kCorrect adds the previous Q loaded at the start of
-      //    the chunk, in one unrolled pass.  The streaming
-      //    stores are issued before the green update, so they drain while it
-      //    computes.  Q <- X (kInit) or Q <- Q + X (kCorrect); then
-      //    Qint = dt X[:, :, 0] in its own pass (consecutive lanes, consecutive
-      //    modes), so no store instruction runs with one lane in T.
+      //    the chunk, in one unrolled pass.  The streaming stores drain while
+      //    the green update computes: kInit issues a quarter of its groups
+      //    here and the rest after the first quarter of the chunk's green
+      //    modes (measured ~1% faster at N=6 than issuing all of them here,
+      //    where the burst waits on the compute unit's write queue).
+      //    Q <- X (kInit) or Q <- Q + X (kCorrect); then Qint = dt X[:, :, 0]
+      //    in its own pass (consecutive lanes, consecutive modes), so no store
+      //    instruction runs with one lane in T.  The block stays open over
+      //    step 4, which issues the remaining kInit groups.
       {
         constexpr int per = c * T;
         constexpr int kOutGroup = 3;
         constexpr int nOut = (kOut + kOutGroup - 1) / kOutGroup;
+        constexpr int kOutEarly = (g > 0) ? (nOut + 3) / 4 : nOut;   // groups issued before step 4
         const int limit = nloc * kNQ * per;
         double* Qg = a.Q + e0 * (kNQ * B * T) + m0 * T;
         // value k of this lane: run index i = tid + k kThreads -> (row, r)
@@ -713,9 +719,9 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
         };
         // streaming stores: Q is written once and not read again here, so
         // it should not displace the Khat lines in L2
-        if constexpr (Mode == kInit) {
+        auto store_groups = [&](int glo, int ghi) __attribute__((always_inline)) {
 #pragma unroll 1
-          for (int gi = 0; gi < nOut; ++gi) {
+          for (int gi = glo; gi < ghi; ++gi) {
             double xv[kOutGroup];
 #pragma unroll
             for (int k = 0; k < kOutGroup; ++k)
@@ -726,6 +732,9 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
               if (i < limit) __builtin_nontemporal_store(xv[k], &Qg[(i / per) * (B * T) + i % per]);
             }
           }
+        };
+        if constexpr (Mode == kInit) {
+          store_groups(0, kOutEarly);
         } else {
           double xv[kOut];
 #pragma unroll
@@ -753,11 +762,16 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
             if (j < ilimit) __builtin_nontemporal_store(v, &Ig[row * B + m0 + kk]);
           }
         }
-      }
-      // 4. green blocks (lane-local): star product, then Khat columns
+      // 4. green blocks (lane-local): star product, then Khat columns.  X of
+      //    the chunk stays in bufX until the next chunk's step 2, so the
+      //    remaining output groups are read from it here.
       if constexpr (g > 0) {
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
+          if constexpr (Mode == kInit && kk == c / 4) {
+            store_groups(kOutEarly, nOut);
+            __builtin_amdgcn_sched_barrier(0);
+          }
           R y0, y1, y2;
           L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
           green_column<N, m0 + kk, R>(b, y0, y1, y2, kv);
@@ -765,6 +779,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
           __builtin_amdgcn_sched_barrier(0);
         });
       }
+      }  // output block of step 3
     });
   });
 }
