@@ -90,6 +90,23 @@ def test_degrees_ragged(kernel, N, n):
     assert rel_l2(Qi, Io).max() <= TOL
 
 
+@pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2"])
+@pytest.mark.parametrize("N,n", [(3, 10), (4, 16), (6, 11)])
+def test_several_groups_with_ragged_tail(kernel, N, n):
+    """Every element against the oracle where the fused kernel's workgroups
+    (4 elements at N=3, 7 at N=4, 5 at N=6) come out as two full groups and a
+    partial one, so the tail group's spare slots and the group offsets are
+    exercised together."""
+    _say(f"[gpu] several_groups_with_ragged_tail kernel={kernel} N={N} n={n}")
+    w = wl.make_small(N, n, seed=200 + N)
+    Q, Qi = _run(w, **KERNELS[kernel])
+    Xo, Io = _oracle(w, list(range(n)))
+    err, erri = rel_l2(Q, Xo), rel_l2(Qi, Io)
+    _say(f"  max rel L2 Q {err.max():.3e}  Qint {erri.max():.3e}")
+    assert np.isfinite(Q).all() and np.isfinite(Qi).all()
+    assert err.max() <= TOL and erri.max() <= TOL
+
+
 @pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
 def test_special_operators(kernel):
     """E = 0 (no source), A = 0 with a stiff source, and all operators zero,
