@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 from paper_2108_10565_amd import workload as wl  # noqa: E402
 
 PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+PEAK_FP32_MFMA_TFLOPS = 157.3    # dense float32 matrix-core peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -220,13 +221,127 @@ def rel_l2(X, Xo):
     return np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))
 
 
+def parity_report(X, Xo):
+    """Max relative L2 error per element and, per quantity, the max over the
+    checked elements of that quantity's relative L2 error (the quantities
+    differ in size by orders of magnitude; each is measured on its own norm)."""
+    el = float(rel_l2(X, Xo).max())
+    ax = tuple(range(2, X.ndim))
+    pq = (np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))).max(axis=0)
+    return dict(max_rel_l2=el, max_rel_l2_per_quantity=dict(zip(wl.QUANTITIES, map(float, pq))),
+                max_rel_l2_worst_quantity=float(pq.max()))
+
+
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), affinity_cpus=len(os.sched_getaffinity(0)))
+
+
+def residual_flops(N: int, khat_nnz: int, star_nnz: int = 54, g_nnz: int = 3) -> int:
+    """FLOP per element of the float64 matrix-free residual of the element
+    system: right-hand side, Z X (T x T per quantity and mode), E* X (diagonal
+    and G couplings), star and Khat products (sparsity-aware, as the solve)."""
+    B, T = wl.n_modes(N), N + 1
+    return (13 * B * T + 2 * 13 * T * T * B + 2 * T * B * (13 + g_nnz) + 2 * 3 * star_nnz * T * (B - 1)
+            + 2 * 13 * T * khat_nnz + 13 * B * T)
+
+
+def refine_bytes(N: int) -> int:
+    """Compulsory HBM bytes per element of one refinement step: read Q0, star,
+    E and the current Q; write the new Q and Qint."""
+    B, T = wl.n_modes(N), N + 1
+    return 8 * (13 * B + 3 * 169 + 169 + 2 * 13 * B * T + 13 * B)
+
+
+def mixed_roofline(N, khat_nnz, K, ms_per_call, n):
+    """Composite bound of the float32 chain + K float64-residual refinement
+    steps: t >= (K+1) F/P32 + K F_res/P64 + bytes/BW (compute and memory
+    terms added, as the steps depend on each other), with F the
+    sparsity-aware FLOP of one solve, P32 the float32 matrix-core peak and
+    P64 the float64 peak.  `frac` = bound time / measured time; `achieved`
+    and `peak` are the path's FLOP over the measured and the bound time."""
+    F = algorithmic_flops(N, khat_nnz)
+    Fr = residual_flops(N, khat_nnz)
+    by = hbm_bytes(N) + K * refine_bytes(N)
+    t_bound = (K + 1) * F / (PEAK_FP32_MFMA_TFLOPS * 1e12) + K * Fr / (PEAK_FP64_VALU_TFLOPS * 1e12) \
+        + by / (PEAK_HBM_GBS * 1e9)
+    t = ms_per_call * 1e-3 / n
+    flops = (K + 1) * F + K * Fr
+    return {"bound": "composite", "achieved": flops / t / 1e12, "peak": flops / t_bound / 1e12,
+            "unit": "TFLOP/s", "frac": t_bound / t, "traffic": None,
+            "bound_ns_per_element": t_bound * 1e9, "measured_ns_per_element": t * 1e9,
+            "flop_per_element": {"fp32_chain": F, "fp64_residual": Fr, "total": flops},
+            "bytes_per_element": by,
+            "peaks_used": {"fp32_tflops": PEAK_FP32_MFMA_TFLOPS, "fp64_tflops": PEAK_FP64_VALU_TFLOPS,
+                           "hbm_gbs": PEAK_HBM_GBS}}
+
+
+def khat_nnz(api, N):
+    _, _, Kh = api.reference_matrices(N)
+    return sum(int((Kh[:, :wl.n_modes(g - 1), wl.n_modes(g - 1):wl.n_modes(g)] != 0).sum())
+               for g in range(1, N + 1))
+
+
+def mixed_leg(args, torch, api, name):
+    """The mixed-precision path on its own workload: the float32 chain alone
+    (K = 0), then K = 1..3 refinement steps, each timed and checked against
+    the oracle on sampled elements (error before refinement and after every
+    step), beside the float64 path on the same inputs."""
+    from oracle import pool as opool
+    log(f"[bench] mixed-precision leg: generating {name}")
+    t = time.perf_counter()
+    w = wl.make_workload(name)
+    ids = wl.oracle_sample(w.n)[::2]
+    log(f"[bench] generated n={w.n} in {time.perf_counter() - t:.1f}s; oracle on {len(ids)} elements {ids}")
+    t = time.perf_counter()
+    Xo, _ = opool.solve_many(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
+    log(f"[bench] oracle done in {time.perf_counter() - t:.1f}s")
+    dev = {k: torch.from_numpy(getattr(w, k)).to("cuda") for k in ("Q0", "star", "E")}
+    torch.cuda.synchronize()
+    nnz = khat_nnz(api, w.N)
+    out = {"workload": name, "elements": w.n, "degree": w.N, "oracle_elements": ids, "steps": {}}
+    for K in range(0, 4):
+        steps = args.steps if K == args.refine_steps else max(3, min(args.steps, 10))
+        tk, Q, Qi = time_path(torch, api, dev, w, steps, min(args.warmup, 3), precision="fp32_refine",
+                              refine_steps=K)
+        rep = parity_report(Q[ids].cpu().numpy(), Xo)
+        del Q, Qi
+        torch.cuda.empty_cache()
+        rec = dict(tk, timed_calls=steps, el_per_s=w.n / (tk["call_ms_mean"] * 1e-3), **rep,
+                   roofline=mixed_roofline(w.N, nnz, K, tk["call_ms_mean"], w.n))
+        out["steps"][str(K)] = rec
+        log(f"[bench] {name} fp32+{K}: {rec['el_per_s'] / 1e6:.3f} M el/s, call {tk['call_ms_mean']:.2f} ms, "
+            f"rel L2 element {rep['max_rel_l2']:.2e} worst quantity {rep['max_rel_l2_worst_quantity']:.2e}, "
+            f"frac of composite bound {rec['roofline']['frac']:.3f}")
+    t64, Q, Qi = time_path(torch, api, dev, w, max(3, min(args.steps, 10)), min(args.warmup, 3),
+                           precision="fp64")
+    rep = parity_report(Q[ids].cpu().numpy(), Xo)
+    del Q, Qi
+    out["fp64_same_inputs"] = dict(t64, el_per_s=w.n / (t64["call_ms_mean"] * 1e-3), **rep)
+    log(f"[bench] {name} fp64: {out['fp64_same_inputs']['el_per_s'] / 1e6:.3f} M el/s, "
+        f"worst quantity {rep['max_rel_l2_worst_quantity']:.2e}")
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n6_heterogeneous_262144")
-    ap.add_argument("--refine-steps", type=int, default=1)
+    ap.add_argument("--mixed-workload", default="n6_heterogeneous_1048576",
+                    help="workload of the mixed-precision leg ('none' to skip it)")
+    ap.add_argument("--refine-steps", type=int, default=1,
+                    help="refinement steps of the headline mixed-precision figure")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(8, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
@@ -275,8 +390,10 @@ def main():
                "sample": f"{len(ids)} elements of {w.name} (ids {ids[:4]}...), dense LU + "
                          f"extended-precision refinement, one element per process, 1 BLAS thread "
                          f"each, wall {wall:.1f}s",
-               "per_element_s_mean": float(np.mean([r[2] for r in res]))}
-        log(f"[bench] cpu baseline {cpu['value']:.3f} el/s over {wall:.1f}s")
+               "per_element_s_mean": float(np.mean([r[2] for r in res])),
+               "blas_threads_per_process": 1, **host_info()}
+        log(f"[bench] cpu baseline {cpu['value']:.3f} el/s over {wall:.1f}s on {cpu['cpu_model']}, "
+            f"nproc {cpu['nproc']}")
 
     import torch
     from paper_2108_10565_amd import api
@@ -286,9 +403,7 @@ def main():
     dev = {k: torch.from_numpy(getattr(w, k)).to("cuda") for k in ("Q0", "star", "E")}
     torch.cuda.synchronize()
 
-    _, _, Kh = api.reference_matrices(w.N)
-    nnz = sum(int((Kh[:, :wl.n_modes(g - 1), wl.n_modes(g - 1):wl.n_modes(g)] != 0).sum())
-              for g in range(1, w.N + 1))
+    nnz = khat_nnz(api, w.N)
     F_alg = algorithmic_flops(w.N, nnz)
     F_dense = dense_block_flops(w.N)
     F_paper, F_exec = api.flops(w.N)
@@ -297,29 +412,18 @@ def main():
     paths = {}
     log("[bench] fp64 path")
     t64, Q, Qi = time_path(torch, api, dev, w, args.steps, args.warmup, precision="fp64")
-    err64 = None
+    rep64 = {}
     if oracle:
         ids = list(oracle)
-        Qs = Q[ids].cpu().numpy()
-        err64 = float(rel_l2(Qs, np.stack([oracle[i][0] for i in ids])).max())
-    paths["fp64"] = dict(t64, el_per_s=w.n / (t64["ms_per_step"] * 1e-3), max_rel_l2=err64)
+        rep64 = parity_report(Q[ids].cpu().numpy(), np.stack([oracle[i][0] for i in ids]))
+    paths["fp64"] = dict(t64, el_per_s=w.n / (t64["ms_per_step"] * 1e-3), **rep64)
     log(f"[bench] fp64 {paths['fp64']['el_per_s'] / 1e6:.3f} M el/s, call {t64['call_ms_mean']:.3f} ms,"
-        f" max rel L2 {err64}")
-    del Q, Qi
+        f" {rep64}")
+    del Q, Qi, dev
     torch.cuda.empty_cache()
-    if not args.skip_fp32:
+    if not args.skip_fp32 and args.mixed_workload != "none":
         try:
-            log(f"[bench] fp32 + {args.refine_steps} refinement step(s) path")
-            t32, Q, Qi = time_path(torch, api, dev, w, args.steps, args.warmup, precision="fp32_refine",
-                                   refine_steps=args.refine_steps)
-            err32 = None
-            if oracle:
-                ids = list(oracle)
-                err32 = float(rel_l2(Q[ids].cpu().numpy(), np.stack([oracle[i][0] for i in ids])).max())
-            paths["fp32_refine"] = dict(t32, refine_steps=args.refine_steps,
-                                        el_per_s=w.n / (t32["ms_per_step"] * 1e-3), max_rel_l2=err32)
-            log(f"[bench] fp32+refine {paths['fp32_refine']['el_per_s'] / 1e6:.3f} M el/s, max rel L2 {err32}")
-            del Q, Qi
+            paths["fp32_refine"] = mixed_leg(args, torch, api, args.mixed_workload)
         except Exception as exc:  # reported, never silently replaced
             paths["fp32_refine"] = dict(error=str(exc))
             log(f"[bench] fp32+refine failed: {exc}")
@@ -346,7 +450,6 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
                      "measured_peak": peaks["fp64_valu_tflops"],
-                     "frac_of_measured_peak": achieved / peaks["fp64_valu_tflops"],
                      "flop_per_element": F_alg,
                      "hbm_gbs": bytes_el * w.n / kernel_s / 1e9,
                      "hbm_frac": bytes_el * w.n / kernel_s / 1e9 / PEAK_HBM_GBS,
@@ -357,8 +460,10 @@ def main():
         "flop_counts_per_element": {"algorithmic_sparse": F_alg, "dense_block": F_dense,
                                     "executed_fused_kernel": F_exec, "paper_upper_bound": F_paper},
     }
-    if "fp32_refine" in paths and "el_per_s" in paths["fp32_refine"]:
-        out["fp32_refine_value"] = paths["fp32_refine"]["el_per_s"]
+    fr = paths.get("fp32_refine", {}).get("steps", {}).get(str(args.refine_steps))
+    if fr:
+        out["fp32_refine_value"] = fr["el_per_s"]
+        out["fp32_refine_roofline"] = fr["roofline"]
     print(json.dumps(out), flush=True)
 
 

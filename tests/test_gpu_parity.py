@@ -1,8 +1,8 @@
 """Parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Bar: per element, relative L2 error over all 13*B*T space-time DOFs in
-physical units <= 1e-10 (float64 path, and the float32 chain after
-refinement); Qint likewise.  Inputs are seeded synthetic workloads from
+Bar: relative L2 error <= 1e-10 per element over all 13*B*T space-time DOFs
+in physical units AND per (element, quantity) over that quantity's B*T DOFs
+(float64 path, and the float32 chain after refinement); Qint likewise.  Inputs are seeded synthetic workloads from
 ``paper_2108_10565_amd.workload``; expected values come only from ``oracle``.
 """
 import os
@@ -13,9 +13,12 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import pool as opool  # noqa: E402
 from oracle import stp as ostp  # noqa: E402
 from paper_2108_10565_amd import api  # noqa: E402
 from paper_2108_10565_amd import workload as wl  # noqa: E402
+
+import parity  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -43,9 +46,13 @@ def _run(w, elements=None, **kw):
     return Q.cpu().numpy(), Qi.cpu().numpy()
 
 
-def rel_l2(X, Xo):
-    axes = tuple(range(1, X.ndim))
-    return np.sqrt(((X - Xo) ** 2).sum(axes)) / np.sqrt((Xo ** 2).sum(axes))
+rel_l2 = parity.rel_l2
+
+
+def _check(Q, Qi, Xo, Io, tol=TOL, label=""):
+    parity.check(Q, Xo, tol, f"{label} Q".strip(), say=_say)
+    if Qi is not None:
+        parity.check(Qi, Io, tol, f"{label} Qint".strip(), say=_say)
 
 
 _ORACLE_CACHE = {}
@@ -54,7 +61,7 @@ _ORACLE_CACHE = {}
 def _oracle(w, idx):
     key = (w.name, tuple(idx))
     if key not in _ORACLE_CACHE:
-        _ORACLE_CACHE[key] = ostp.solve(w.N, w.star[idx], w.E[idx], w.Q0[idx], w.dt)
+        _ORACLE_CACHE[key] = opool.solve_many(w.N, w.star[idx], w.E[idx], w.Q0[idx], w.dt)
     return _ORACLE_CACHE[key]
 
 
@@ -69,11 +76,7 @@ def test_n3_homogeneous_all_64(cfg1, kernel):
     Q, Qi = _run(cfg1, **KERNELS[kernel])
     idx = list(range(64))
     Xo, Io = _oracle(cfg1, idx)
-    err = rel_l2(Q, Xo)
-    erri = rel_l2(Qi, Io)
-    _say(f"  max rel L2 Q {err.max():.3e}  Qint {erri.max():.3e}")
-    assert np.isfinite(Q).all()
-    assert err.max() <= TOL and erri.max() <= TOL
+    _check(Q, Qi, Xo, Io)
 
 
 @pytest.mark.parametrize("kernel", list(KERNELS))
@@ -84,10 +87,7 @@ def test_degrees_ragged(kernel, N, n):
     w = wl.make_small(N, n, seed=100 + N)
     Q, Qi = _run(w, **KERNELS[kernel])
     Xo, Io = _oracle(w, list(range(n)))
-    err = rel_l2(Q, Xo)
-    _say(f"  max rel L2 {err.max():.3e}")
-    assert err.max() <= TOL
-    assert rel_l2(Qi, Io).max() <= TOL
+    _check(Q, Qi, Xo, Io)
 
 
 @pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2"])
@@ -101,10 +101,7 @@ def test_several_groups_with_ragged_tail(kernel, N, n):
     w = wl.make_small(N, n, seed=200 + N)
     Q, Qi = _run(w, **KERNELS[kernel])
     Xo, Io = _oracle(w, list(range(n)))
-    err, erri = rel_l2(Q, Xo), rel_l2(Qi, Io)
-    _say(f"  max rel L2 Q {err.max():.3e}  Qint {erri.max():.3e}")
-    assert np.isfinite(Q).all() and np.isfinite(Qi).all()
-    assert err.max() <= TOL and erri.max() <= TOL
+    _check(Q, Qi, Xo, Io)
 
 
 @pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
@@ -121,10 +118,8 @@ def test_special_operators(kernel):
     star[3] = 0.0; E[3] = 0.0
     Q, Qi = api.predict(_dev(w.Q0), _dev(star), _dev(E), w.dt, N, **KERNELS[kernel])
     torch.cuda.synchronize()
-    Xo, Io = ostp.solve(N, star, E, w.Q0, w.dt)
-    err = rel_l2(Q.cpu().numpy(), Xo)
-    _say(f"  rel L2 per element {err}")
-    assert err.max() <= TOL
+    Xo, Io = opool.solve_many(N, star, E, w.Q0, w.dt)
+    _check(Q.cpu().numpy(), Qi.cpu().numpy(), Xo, Io)
     # all-zero operators: constant in time
     np.testing.assert_allclose(Q.cpu().numpy()[3][:, :, 0], w.Q0[3], rtol=0, atol=1e-15)
 
@@ -142,8 +137,8 @@ def test_empty_and_no_qint(kernel):
                         **KERNELS[kernel])
     torch.cuda.synchronize()
     assert Qi is None
-    Xo, _ = _oracle(w, [0, 1])
-    assert rel_l2(Q.cpu().numpy(), Xo).max() <= TOL
+    Xo, Io = _oracle(w, [0, 1])
+    _check(Q.cpu().numpy(), None, Xo, Io)
 
 
 @pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
@@ -174,9 +169,9 @@ def test_validate_reports_bad_inputs():
 def test_kernels_agree_with_each_other():
     _say("[gpu] kernels agree")
     w = wl.make_small(5, 11, seed=21)
-    Qa, _ = _run(w, **KERNELS["reference"])
-    Qb, _ = _run(w, **KERNELS["fused_fp64"])
-    assert rel_l2(Qb, Qa).max() <= TOL
+    Qa, Ia = _run(w, **KERNELS["reference"])
+    Qb, Ib = _run(w, **KERNELS["fused_fp64"])
+    _check(Qb, Ib, Qa, Ia, label="fused vs reference")
 
 
 def test_fp32_refinement_progression():
@@ -188,11 +183,16 @@ def test_fp32_refinement_progression():
     errs = []
     for k in range(0, 4):
         Q, Qi = _run(w, precision="fp32_refine", refine_steps=k)
-        errs.append(float(rel_l2(Q, Xo).max()))
-        assert rel_l2(Qi, Io).max() <= max(10 * errs[-1], TOL)
-    _say(f"  max rel L2 after 0..3 refinement steps: {['%.2e' % e for e in errs]}")
-    assert errs[0] <= 1e-4                 # float32 chain alone
-    assert errs[1] <= TOL and errs[2] <= TOL and errs[3] <= TOL
+        if k == 0:
+            # float32 chain alone: every quantity to float32 accuracy
+            el, per_q = parity.summary(Q, Xo)
+            _say(f"  chain alone: element {el:.2e}, per quantity {parity.fmt(per_q)}")
+            errs.append(float(max(el, per_q.max())))
+            assert errs[0] <= 1e-4
+        else:
+            errs.append(parity.check(Q, Xo, TOL, f"after {k} step(s) Q", say=_say))
+            parity.check(Qi, Io, TOL, f"after {k} step(s) Qint", say=_say)
+    _say(f"  worst rel L2 after 0..3 refinement steps: {['%.2e' % e for e in errs]}")
     assert errs[1] < errs[0] * 1e-3
 
 
@@ -206,43 +206,41 @@ def test_stiffness_sweep_per_decade():
     pick = []
     for d in range(-2, 6):
         pick += list(np.where(dec == d)[0][:2])
-    Xo, _ = ostp.solve(5, w.star[pick], w.E[pick], w.Q0[pick], w.dt)
+    Xo, Io = opool.solve_many(5, w.star[pick], w.E[pick], w.Q0[pick], w.dt)
     for kw in (dict(precision="fp64"), dict(precision="fp32_refine", refine_steps=1),
                dict(precision="fp32_refine", refine_steps=2)):
-        Q, _ = _run(w, **kw)
-        err = rel_l2(Q[pick], Xo)
-        per = {int(d): float(err[np.array(dec[pick]) == d].max()) for d in sorted(set(dec[pick]))}
-        _say(f"  {kw}: max rel L2 per decade {per}")
-        assert err.max() <= TOL
+        Q, Qi = _run(w, **kw)
+        worst = np.maximum(rel_l2(Q[pick], Xo), parity.rel_l2_per_quantity(Q[pick], Xo).max(axis=1))
+        per = {int(d): float(worst[np.array(dec[pick]) == d].max()) for d in sorted(set(dec[pick]))}
+        _say(f"  {kw}: worst rel L2 (element or quantity) per decade {per}")
+        _check(Q[pick], Qi[pick], Xo, Io, label=str(kw))
 
 
-def _full_size(name, kw, nsample):
+def _full_size(name, kw):
     w = wl.make_workload(name)
-    ids = wl.oracle_sample(w.n)[:nsample]
-    _say(f"  generated {name} n={w.n}; sampled elements {ids}")
+    ids = wl.oracle_sample(w.n)
+    _say(f"  generated {name} n={w.n}; {len(ids)} sampled elements {ids}")
     Q, Qi = api.predict(_dev(w.Q0), _dev(w.star), _dev(w.E), w.dt, w.N, **kw)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(Q).all()) and bool(torch.isfinite(Qi).all())
     Qs, Is = Q[ids].cpu().numpy(), Qi[ids].cpu().numpy()
     del Q, Qi
     torch.cuda.empty_cache()
-    Xo, Io = ostp.solve(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
-    err, erri = rel_l2(Qs, Xo), rel_l2(Is, Io)
-    _say(f"  max rel L2 Q {err.max():.3e} Qint {erri.max():.3e}")
-    assert err.max() <= TOL and erri.max() <= TOL
+    Xo, Io = _oracle(w, ids)
+    _check(Qs, Is, Xo, Io)
 
 
 def test_full_size_n6_262144_fp64_sampled():
     """The benchmark's workload and launch: all 262,144 N=6 elements in one
     call, sampled elements checked against the oracle, all outputs finite."""
     _say("[gpu] full size n6_heterogeneous_262144 fp64")
-    _full_size("n6_heterogeneous_262144", dict(precision="fp64"), 4)
+    _full_size("n6_heterogeneous_262144", dict(precision="fp64"))
 
 
 def test_full_size_n6_1048576_fp32_refine_sampled():
     """1,048,576 N=6 elements through the float32 chain + one refinement step."""
     _say("[gpu] full size n6_heterogeneous_1048576 fp32_refine")
-    _full_size("n6_heterogeneous_1048576", dict(precision="fp32_refine", refine_steps=1), 2)
+    _full_size("n6_heterogeneous_1048576", dict(precision="fp32_refine", refine_steps=1))
 
 
 def _general_operators(N, n, seed, chain_prob=0.35):
@@ -274,14 +272,11 @@ def test_general_operators_dense_star_coupling_chains(kernel, N, n):
     _say(f"[gpu] general operators kernel={kernel} N={N} n={n}")
     if (N, n) not in _GENERAL_CACHE:
         w, star, E = _general_operators(N, n, seed=60 + N)
-        _GENERAL_CACHE[(N, n)] = (w, star, E) + tuple(ostp.solve(N, star, E, w.Q0, w.dt))
+        _GENERAL_CACHE[(N, n)] = (w, star, E) + tuple(opool.solve_many(N, star, E, w.Q0, w.dt))
     w, star, E, Xo, Io = _GENERAL_CACHE[(N, n)]
     Q, Qi = api.predict(_dev(w.Q0), _dev(star), _dev(E), w.dt, N, **KERNELS[kernel])
     torch.cuda.synchronize()
-    err = rel_l2(Q.cpu().numpy(), Xo)
-    _say(f"  max rel L2 {err.max():.3e}")
-    assert err.max() <= TOL
-    assert rel_l2(Qi.cpu().numpy(), Io).max() <= TOL
+    _check(Q.cpu().numpy(), Qi.cpu().numpy(), Xo, Io)
 
 
 @pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2"])
@@ -295,12 +290,10 @@ def test_one_dense_star_row_in_a_group(kernel):
     star = w.star.copy()
     rng = np.random.default_rng(71)
     star[3, :, 0, :] += rng.standard_normal((3, 13)) * np.abs(star[3]).max() * 1e-3
-    Q, _ = api.predict(_dev(w.Q0), _dev(star), _dev(w.E), w.dt, N, **KERNELS[kernel])
+    Q, Qi = api.predict(_dev(w.Q0), _dev(star), _dev(w.E), w.dt, N, **KERNELS[kernel])
     torch.cuda.synchronize()
-    Xo, _ = ostp.solve(N, star, w.E, w.Q0, w.dt)
-    err = rel_l2(Q.cpu().numpy(), Xo)
-    _say(f"  max rel L2 {err.max():.3e}")
-    assert err.max() <= TOL
+    Xo, Io = opool.solve_many(N, star, w.E, w.Q0, w.dt)
+    _check(Q.cpu().numpy(), Qi.cpu().numpy(), Xo, Io)
 
 
 def test_full_size_n5_stiffness_524288_per_decade():
@@ -315,18 +308,18 @@ def test_full_size_n5_stiffness_524288_per_decade():
     for d in range(-2, 6):
         ids += [int(i) for i in np.where(dec == d)[0][:2]]
     _say(f"  decades {sorted(set(dec[ids].tolist()))}, elements {ids}")
-    Xo, Io = ostp.solve(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
+    Xo, Io = opool.solve_many(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
     dQ0, dstar, dE = _dev(w.Q0), _dev(w.star), _dev(w.E)
     for kw in (dict(precision="fp64"), dict(precision="fp32_refine", refine_steps=1),
                dict(precision="fp32_refine", refine_steps=2)):
         Q, Qi = api.predict(dQ0, dstar, dE, w.dt, w.N, **kw)
         torch.cuda.synchronize()
         assert bool(torch.isfinite(Q).all())
-        err = rel_l2(Q[ids].cpu().numpy(), Xo)
-        erri = rel_l2(Qi[ids].cpu().numpy(), Io)
-        per = {int(d): float(err[dec[ids] == d].max()) for d in sorted(set(dec[ids].tolist()))}
-        _say(f"  {kw}: max rel L2 per decade {per}")
-        assert err.max() <= TOL and erri.max() <= TOL
+        Qs, Is = Q[ids].cpu().numpy(), Qi[ids].cpu().numpy()
+        worst = np.maximum(rel_l2(Qs, Xo), parity.rel_l2_per_quantity(Qs, Xo).max(axis=1))
+        per = {int(d): float(worst[dec[ids] == d].max()) for d in sorted(set(dec[ids].tolist()))}
+        _say(f"  {kw}: worst rel L2 (element or quantity) per decade {per}")
+        _check(Qs, Is, Xo, Io, label=str(kw))
         del Q, Qi
         torch.cuda.empty_cache()
 
@@ -336,17 +329,22 @@ def test_full_size_n6_1048576_refinement_progression():
     refinement steps, on oracle-checked sampled elements, beside float64."""
     _say("[gpu] full size n6_heterogeneous_1048576 refinement progression")
     w = wl.make_workload("n6_heterogeneous_1048576")
-    ids = wl.oracle_sample(w.n)[:3]
-    Xo, _ = ostp.solve(w.N, w.star[ids], w.E[ids], w.Q0[ids], w.dt)
+    ids = wl.oracle_sample(w.n)
+    Xo, _ = _oracle(w, ids)
     dQ0, dstar, dE = _dev(w.Q0), _dev(w.star), _dev(w.E)
     errs = {}
     for name, kw in (("fp64", dict(precision="fp64")),) + tuple(
             (f"fp32+{k}", dict(precision="fp32_refine", refine_steps=k)) for k in range(4)):
         Q, _ = api.predict(dQ0, dstar, dE, w.dt, w.N, with_qint=False, **kw)
         torch.cuda.synchronize()
-        errs[name] = float(rel_l2(Q[ids].cpu().numpy(), Xo).max())
+        Qs = Q[ids].cpu().numpy()
         del Q
         torch.cuda.empty_cache()
-    _say(f"  max rel L2: {errs}")
-    assert errs["fp64"] <= TOL and errs["fp32+0"] <= 1e-4
-    assert all(errs[f"fp32+{k}"] <= TOL for k in (1, 2, 3))
+        if name == "fp32+0":
+            el, per_q = parity.summary(Qs, Xo)
+            _say(f"  {name}: element {el:.2e}, per quantity {parity.fmt(per_q)}")
+            errs[name] = float(max(el, per_q.max()))
+        else:
+            errs[name] = parity.check(Qs, Xo, TOL, name, say=_say)
+    _say(f"  worst rel L2 (element or quantity): {errs}")
+    assert errs["fp32+0"] <= 1e-4
