@@ -87,6 +87,10 @@ typedef enum stp_precision {
  * the fused register-resident kernel.  Same results up to rounding; kept
  * as an independent GPU implementation and for debugging. */
 #define STP_FLAG_REFERENCE_KERNEL 1u
+/* STP_FP32_REFINE only: run the float32 chain's green-block update on the
+ * vector ALU instead of the matrix cores (same results up to float32
+ * rounding; kept to compare the two). */
+#define STP_FLAG_VALU_FLOAT_CHAIN 2u
 
 /* Create / destroy a handle.  No device work is done by either. */
 stp_status stp_create(stp_handle* handle);
@@ -148,6 +152,31 @@ stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z,
  * "tab:flop-count"), and the count this library executes in its fused
  * float64 kernel (useful FLOP: dense star matrices, non-zero Khat entries). */
 stp_status stp_flops(int degree, double* paper_bound, double* executed);
+
+/* ---- Prediction without a caller workspace --------------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments (minus the workspace), kernels and results as stp_predict; the
+ * mixed-precision path's residual buffer is a device array inside the
+ * library instead, of stp_static_scratch_bytes() bytes (256 MiB) per device,
+ * which each device holds from the first call on it until the process ends.
+ * The call allocates nothing and does not synchronise.
+ *  - A call whose stp_workspace_size exceeds the array returns
+ *    STP_EWORKSPACE before launching anything (at N=6 with refinement: up to
+ *    8,779 elements per call; split larger batches).  STP_FP64 and
+ *    refine_steps == 0 need no scratch and have no size limit.
+ *  - hip_stream must belong to the current device (STP_EINVAL otherwise).
+ *  - Every call on a device shares that device's array, and no call relies
+ *    on what an earlier one left in it.  Calls that overlap in time on one
+ *    device (two streams, or two host threads) race on it and give wrong
+ *    results; calls ordered on one stream do not. */
+size_t stp_static_scratch_bytes(void);
+stp_status stp_predict_static(stp_handle handle, void* hip_stream, int degree,
+                              int64_t n_elements, double dt, const double* star,
+                              const double* E, const double* Q0, double* Q,
+                              double* Qint, stp_precision precision,
+                              int refine_steps, unsigned flags);
 
 /* ---- Several batches in one call, and a replayable graph of them ---------
  *

@@ -23,7 +23,8 @@ MAX_DEGREE = 7
 EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "stp_validate",
             "stp_reference_matrices", "stp_flops", "stp_batched_workspace_size",
             "stp_predict_batched", "stp_graph_create", "stp_graph_launch", "stp_graph_destroy",
-            "stp_measure_peaks", "stp_status_string", "stp_last_error")
+            "stp_measure_peaks", "stp_static_scratch_bytes", "stp_predict_static",
+            "stp_status_string", "stp_last_error")
 
 
 class StpBatch(ctypes.Structure):
@@ -67,6 +68,10 @@ def load(path: str = LIB_PATH):
     lib.stp_predict.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
                                 ctypes.c_int, ctypes.c_int, vp, sz, ctypes.c_uint]
     lib.stp_validate.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp]
+    lib.stp_static_scratch_bytes.argtypes = []
+    lib.stp_static_scratch_bytes.restype = sz
+    lib.stp_predict_static.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_uint]
     lib.stp_reference_matrices.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.stp_flops.argtypes = [ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     pb = ctypes.POINTER(StpBatch)
@@ -84,7 +89,7 @@ def load(path: str = LIB_PATH):
     lib.stp_last_error.argtypes = [vp]
     lib.stp_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("stp_status_string", "stp_last_error"):
+        if name not in ("stp_status_string", "stp_last_error", "stp_static_scratch_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -63,6 +63,28 @@ def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine
     return Q, Qint
 
 
+def static_scratch_bytes() -> int:
+    """stp_static_scratch_bytes: size of the library's per-device scratch."""
+    return int(_lib.load().stp_static_scratch_bytes())
+
+
+def predict_static(Q0, star, E, dt: float, degree: int, Q, Qint=None, precision: str = "fp64",
+                   refine_steps: int = 1, reference_kernel: bool = False, stream=None):
+    """stp_predict_static: as predict(), into the caller's Q (and Qint, may be
+    None), with no workspace: the library's per-device scratch is used and
+    nothing is allocated here or in the library."""
+    import torch
+    h = _h()
+    n = _check_inputs(Q0, star, E, degree)
+    if stream is None:
+        stream = torch.cuda.current_stream(Q0.device)
+    flags = _lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0
+    h.check(h.lib.stp_predict_static(h.ptr, ctypes.c_void_p(stream.cuda_stream), degree, n, float(dt),
+                                     _ptr(star), _ptr(E), _ptr(Q0), _ptr(Q), _ptr(Qint), _PREC[precision],
+                                     refine_steps, flags))
+    return Q, Qint
+
+
 def _check_inputs(Q0, star, E, degree):
     import torch
     n = int(Q0.shape[0])

@@ -50,29 +50,31 @@ inline size_t workspace_bytes(int N, int64_t n, int precision, int refine_steps)
 hipError_t launch_reference_kernel(int N, const PredictArgs& a, hipStream_t stream);
 // The fused kernel is compiled once per degree (STP_DEGREE); each object
 // defines the specialisation for its degree.
+// valu_float_chain: run the float32 chain's green update on the vector ALU
+// instead of the matrix cores (kept for comparison measurements).
 template <int N>
 hipError_t launch_fused_degree(const PredictArgs& a, int precision, int refine_steps, float* workspace,
-                               hipStream_t stream);
-template <> hipError_t launch_fused_degree<0>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<1>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<2>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<3>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<4>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<5>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<6>(const PredictArgs&, int, int, float*, hipStream_t);
-template <> hipError_t launch_fused_degree<7>(const PredictArgs&, int, int, float*, hipStream_t);
+                               bool valu_float_chain, hipStream_t stream);
+template <> hipError_t launch_fused_degree<0>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<1>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<2>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<3>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<4>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<5>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<6>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+template <> hipError_t launch_fused_degree<7>(const PredictArgs&, int, int, float*, bool, hipStream_t);
 
 inline hipError_t launch_fused_kernel(int N, const PredictArgs& a, int precision, int refine_steps,
-                                      float* workspace, hipStream_t stream) {
+                                      float* workspace, bool valu_float_chain, hipStream_t stream) {
   switch (N) {
-    case 0: return launch_fused_degree<0>(a, precision, refine_steps, workspace, stream);
-    case 1: return launch_fused_degree<1>(a, precision, refine_steps, workspace, stream);
-    case 2: return launch_fused_degree<2>(a, precision, refine_steps, workspace, stream);
-    case 3: return launch_fused_degree<3>(a, precision, refine_steps, workspace, stream);
-    case 4: return launch_fused_degree<4>(a, precision, refine_steps, workspace, stream);
-    case 5: return launch_fused_degree<5>(a, precision, refine_steps, workspace, stream);
-    case 6: return launch_fused_degree<6>(a, precision, refine_steps, workspace, stream);
-    case 7: return launch_fused_degree<7>(a, precision, refine_steps, workspace, stream);
+    case 0: return launch_fused_degree<0>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 1: return launch_fused_degree<1>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 2: return launch_fused_degree<2>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 3: return launch_fused_degree<3>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 4: return launch_fused_degree<4>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 5: return launch_fused_degree<5>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 6: return launch_fused_degree<6>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 7: return launch_fused_degree<7>(a, precision, refine_steps, workspace, valu_float_chain, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -784,6 +784,361 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   });
 }
 
+// ---------------------------------------------------------------------------
+// Float32 chain with the green-block update on the matrix cores.
+//
+// The green update of a chunk is a product with a shared left operand:
+//   b[n, col] -= sum_k Khat(k)[n] Y[k, col],   k = (mode mm of the chunk, direction j),
+// Y[k, col] = (A^{j*} X[:, mm, u])_p for column col = (element, quantity p, time
+// mode u), n below the block start.  It runs as v_mfma_f32_16x16x4f32 with
+// float32 accumulation: wave w keeps the right-hand side rows below the top
+// degree block of its own 64 columns (4 column tiles of 16) in accumulator
+// tiles of 16 rows; the A operand is a 16-row slice of -Khat read from a
+// generated table, the B operand the wave's Y rows, which its lanes compute
+// (sparse star rows, vector ALU) into a per-wave LDS buffer.  The dark-blue
+// solves stay float64 on the vector ALU, and the matrix-core instructions of a
+// chunk overlap the vector work that follows them.  Accumulator layout of
+// the 16x16x4 instruction: lane l holds column l % 16, rows 4 (l / 16) + r,
+// r = 0..3; A operand A[l % 16][l / 16]; B operand B[l / 16][l % 16].
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMG = 4;        // modes per k group: 3 k-blocks of 4 (mode, direction) pairs
+constexpr int kYStride = 80;  // floats per k row of a wave's Y buffer: 64 columns, padded against bank conflicts
+
+template <int N>
+struct MfmaCfg {
+  using C = Cfg<N>;
+  static constexpr int kWaves = C::kThreads / 64;
+  static constexpr int RN = (C::LN + 15) / 16;  // accumulator row tiles (rows below the top block)
+  static constexpr int RA = RN > 0 ? RN : 1;
+  static constexpr int kRealCols = C::kElems * C::kCols;
+};
+
+template <int N>
+struct SharedM {
+  Shared<N, float> s;
+  float ybuf[MfmaCfg<N>::kWaves][3 * kMG][kYStride];
+};
+
+template <int N>
+__device__ __forceinline__ const float* khat_mfma() {
+  if constexpr (N == 0) return stp_gen::kKhatMfma0;
+  else if constexpr (N == 1) return stp_gen::kKhatMfma1;
+  else if constexpr (N == 2) return stp_gen::kKhatMfma2;
+  else if constexpr (N == 3) return stp_gen::kKhatMfma3;
+  else if constexpr (N == 4) return stp_gen::kKhatMfma4;
+  else if constexpr (N == 5) return stp_gen::kKhatMfma5;
+  else if constexpr (N == 6) return stp_gen::kKhatMfma6;
+  else return stp_gen::kKhatMfma7;
+}
+
+// Algorithm 3 in float32 with the green update on the matrix cores (dark-blue
+// solves in float64).  kInit: b = Q0 (S^-1 w), Q <- X.  kCorrect: b = the
+// residual in `rin` (float), Q <- Q + X.
+template <int N, int Mode>
+__global__ __launch_bounds__(Cfg<N>::kThreads) void mfma_solve_kernel(PredictArgs a, const float* rin) {
+  using C = Cfg<N>;
+  using MC = MfmaCfg<N>;
+  using R = float;
+  constexpr int B = C::B, T = C::T, kE = C::kElems, kThreads = C::kThreads;
+  __shared__ SharedM<N> shm;
+  Shared<N, R>& sh = shm.s;
+  R* const bufB = sh.u.c.bufB;
+  R* const bufX = sh.u.c.bufX;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, lrow = lane >> 4, lcol = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
+  const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
+  const int nloc = static_cast<int>(nloc64);
+  const LaneId<N> lid(tid);
+  const int es = lid.es, p = lid.p, u = lid.u;
+  const bool active = es < nloc;
+  const int cb = C::blk(es, p);
+  float* const yb = &shm.ybuf[wave][0][0];
+
+  // Column tiles of this wave holding real columns (wave-uniform), and the
+  // chunk-buffer offset blk(e, p) + u of this lane's column in each tile.
+  const int nct = __builtin_amdgcn_readfirstlane(
+      (MC::kRealCols - 64 * wave) >= 64 ? 4 : ((MC::kRealCols - 64 * wave) > 0 ? (MC::kRealCols - 64 * wave + 15) / 16 : 0));
+  int coff[4];
+  v4f acc[4][MC::RA];
+  static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
+    constexpr int ct = decltype(ctc)::value;
+    const LaneId<N> cid(64 * wave + 16 * ct + lcol);
+    coff[ct] = C::blk(cid.es, cid.p) + cid.u;
+    const bool cact = cid.es < nloc;
+    const int64_t crow = (cact ? e0 + cid.es : 0) * kNQ + cid.p;
+    // accumulators: b rows below the top block
+    static_for<0, MC::RA>([&](auto rtc) __attribute__((always_inline)) {
+      constexpr int rt = decltype(rtc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + 4 * lrow + r;
+        float v = 0.0f;
+        if (cact && row < C::LN) {
+          if constexpr (Mode == kInit) v = static_cast<float>(a.Q0[crow * B + row] * sinv_w(cid.u));
+          else v = rin[crow * (B * T) + row * T + cid.u];
+        }
+        acc[ct][rt][r] = v;
+      }
+    });
+  });
+  for (int i = lane; i < 3 * kMG * kYStride; i += 64) yb[i] = 0.0f;
+  const float* const ktab = khat_mfma<N>();
+
+  constexpr int kFirstC = chunk_size(N, C::kChunk, 0), kFirstM = chunk_start(N, C::kChunk, 0);
+  constexpr int kFirstPer = (kE * kNQ * kFirstC + kThreads - 1) / kThreads;
+  double q_first[kFirstPer];
+  if constexpr (Mode == kInit) {
+#pragma unroll
+    for (int k = 0; k < kFirstPer; ++k) {
+      const int i = tid + k * kThreads;
+      const int ee = i / (kNQ * kFirstC), pp = (i / kFirstC) % kNQ, kk = i % kFirstC;
+      q_first[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + kFirstM + kk] : 0.0;
+    }
+  }
+  LaneSetup<N, R> L;
+  L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
+  const int pb = C::blk(es, L.gp);
+  using ZS = stp_gen::ZinvSparse<N>;
+  const int cz0 = cb + ZS::col[2 * u], cz1 = cb + ZS::col[2 * u + 1];
+  const double zv0 = ZS::val[2 * u], zv1 = ZS::val[2 * u + 1];
+  const bool wave_stiff = __builtin_amdgcn_ballot_w64(sh.G[es][p][p] != 0.0) != 0;
+  const bool wave_coupled = __builtin_amdgcn_ballot_w64(L.gcount == 1) != 0;
+
+  static_for<0, N + 1>([&](auto gi) __attribute__((always_inline)) {
+    constexpr int g = N - decltype(gi)::value;
+    static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
+      constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
+      constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
+      constexpr int kOut = (kE * kNQ * c * T + kThreads - 1) / kThreads;
+      // 1. right-hand side of the chunk to LDS
+      if constexpr (g == N) {
+        if constexpr (Mode == kInit) {
+          constexpr int per_thread = (kE * kNQ * c + kThreads - 1) / kThreads;
+          double q[per_thread];
+          if constexpr (decltype(ci)::value == 0) {
+#pragma unroll
+            for (int k = 0; k < per_thread; ++k) q[k] = q_first[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < per_thread; ++k) {
+              const int i = tid + k * kThreads;
+              const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+              q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < per_thread; ++k) {
+            const int i = tid + k * kThreads;
+            const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
+            if (ee < nloc) {
+#pragma unroll
+              for (int uu = 0; uu < T; ++uu) bufB[C::blk(ee, pp) + kk * T + uu] = static_cast<R>(q[k] * sinv_w(uu));
+            }
+          }
+        } else {
+          stage_rows<N, R, c * T>(bufB, rin, e0, m0 * T, nloc, tid);
+        }
+      } else {
+        // rows m0 .. m0 + c - 1 leave the accumulators of this wave's columns
+        constexpr int rt0 = m0 / 16, rt1 = (m0 + c - 1) / 16;
+        static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
+          constexpr int ct = decltype(ctc)::value;
+          if (ct < nct) {
+            static_for<rt0, rt1 + 1>([&](auto rtc) __attribute__((always_inline)) {
+              constexpr int rt = decltype(rtc)::value;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int mm = 16 * rt + 4 * lrow + r - m0;
+                if (mm >= 0 && mm < c) bufB[coff[ct] + mm * T] = acc[ct][rt][r];
+              }
+            });
+          }
+        });
+      }
+      __syncthreads();
+      // 2. dark-blue blocks and G coupling (float64)
+      if (L.closure) {
+        auto dark_blue = [&](auto stiff_c, auto coupled_c) __attribute__((always_inline)) {
+          constexpr bool kStiff = decltype(stiff_c)::value, kCoupled = decltype(coupled_c)::value;
+          double zr[T], drr[T];
+          if constexpr (kStiff) {
+#pragma unroll
+            for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
+          }
+          if constexpr (kCoupled) {
+#pragma unroll
+            for (int v = 0; v < T; ++v) drr[v] = sh.dr[tid][v];
+          }
+          static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+            constexpr int kk = decltype(k)::value;
+            double x;
+            if constexpr (kStiff) {
+              x = 0.0;
+#pragma unroll
+              for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+            } else {
+              x = fma(zv0, static_cast<double>(bufB[cz0 + kk * T]), zv1 * static_cast<double>(bufB[cz1 + kk * T]));
+            }
+            if constexpr (kCoupled) {
+#pragma unroll
+              for (int v = 0; v < T; ++v) x = fma(drr[v], static_cast<double>(bufB[pb + kk * T + v]), x);
+            }
+            bufX[cb + kk * T + u] = static_cast<R>(x);
+          });
+        };
+        using yes = std::true_type;
+        using no = std::false_type;
+        if (wave_stiff) {
+          if (wave_coupled) dark_blue(yes{}, yes{});
+          else dark_blue(yes{}, no{});
+        } else {
+          if (wave_coupled) dark_blue(no{}, yes{});
+          else dark_blue(no{}, no{});
+        }
+      } else {
+        double zr[T];
+#pragma unroll
+        for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
+        static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+          constexpr int kk = decltype(k)::value;
+          double x = 0.0;
+#pragma unroll
+          for (int v = 0; v < T; ++v) x = fma(zr[v], static_cast<double>(bufB[cb + kk * T + v]), x);
+          bufX[cb + kk * T + u] = static_cast<R>(x);
+        });
+        for (int r = 1; r <= L.maxlevel; ++r) {
+          __syncthreads();
+          if (L.mylevel == r) {
+            static_for<0, c>([&](auto k) __attribute__((always_inline)) {
+              constexpr int kk = decltype(k)::value;
+              double accd[T];
+#pragma unroll
+              for (int v = 0; v < T; ++v) accd[v] = static_cast<double>(bufB[cb + kk * T + v]);
+              for (int q = p + 1; q < kNQ; ++q) {
+                const double gq = sh.G[es][p][q];
+                if (gq != 0.0) {
+                  const int qb = C::blk(es, q) + kk * T;
+#pragma unroll
+                  for (int v = 0; v < T; ++v) accd[v] = fma(gq, static_cast<double>(bufX[qb + v]), accd[v]);
+                }
+              }
+              double x = 0.0;
+#pragma unroll
+              for (int v = 0; v < T; ++v) x = fma(zr[v], accd[v], x);
+              bufX[cb + kk * T + u] = static_cast<R>(x);
+            });
+          }
+        }
+      }
+      __syncthreads();
+      // 3. outputs of the chunk: Q <- X (kInit) or Q <- Q + X (kCorrect) in a
+      //    rolled loop of groups of three values per lane, contiguous runs,
+      //    streaming stores; then Qint
+      {
+        constexpr int per = c * T;
+        const int limit = nloc * kNQ * per;
+        double* Qg = a.Q + e0 * (kNQ * B * T) + m0 * T;
+        auto lds_index = [&](int i) __attribute__((always_inline)) {
+          const int row = i / per;
+          const int ee = row / kNQ;
+          return C::blk(ee < kE ? ee : kE, row % kNQ) + i % per;
+        };
+        {
+          constexpr int kOutGroup = 3;
+          constexpr int nOut = (kOut + kOutGroup - 1) / kOutGroup;
+#pragma unroll 1
+          for (int gi = 0; gi < nOut; ++gi) {
+            double xv[kOutGroup], qv[kOutGroup];
+#pragma unroll
+            for (int k = 0; k < kOutGroup; ++k) {
+              const int i = tid + (gi * kOutGroup + k) * kThreads;
+              qv[k] = (Mode == kCorrect && i < limit) ? Qg[(i / per) * (B * T) + i % per] : 0.0;
+              xv[k] = static_cast<double>(bufX[lds_index(i)]);
+            }
+#pragma unroll
+            for (int k = 0; k < kOutGroup; ++k) {
+              const int i = tid + (gi * kOutGroup + k) * kThreads;
+              if (i < limit) __builtin_nontemporal_store(xv[k] + qv[k], &Qg[(i / per) * (B * T) + i % per]);
+            }
+          }
+        }
+        if (a.Qint) {
+          double* Ig = a.Qint + e0 * (kNQ * B);
+          constexpr int kInt = (kE * kNQ * c + kThreads - 1) / kThreads;
+          const int ilimit = nloc * kNQ * c;
+#pragma unroll
+          for (int k = 0; k < kInt; ++k) {
+            const int j = tid + k * kThreads;
+            const int row = j / c, kk = j % c;
+            const int ee = row / kNQ, pp = row % kNQ;
+            double v = a.dt * static_cast<double>(bufX[C::blk(ee < kE ? ee : kE, pp) + kk * T]);
+            if constexpr (Mode == kCorrect) v += j < ilimit ? Ig[row * B + m0 + kk] : 0.0;
+            if (j < ilimit) __builtin_nontemporal_store(v, &Ig[row * B + m0 + kk]);
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // 4. green blocks on the matrix cores, in groups of kMG modes
+      if constexpr (g > 0) {
+        constexpr int RG = (block_start(g) + 15) / 16;   // row tiles holding rows below block g
+        static_for<0, (c + kMG - 1) / kMG>([&](auto grc) __attribute__((always_inline)) {
+          constexpr int mg0 = decltype(grc)::value * kMG;
+          constexpr int gm = (c - mg0) < kMG ? (c - mg0) : kMG;
+          constexpr int nkb = (3 * gm + 3) / 4;
+          __builtin_amdgcn_sched_barrier(0);
+          // star products of the group's modes -> Y rows k = 3 mm + j of this wave
+          static_for<0, gm>([&](auto mmc) __attribute__((always_inline)) {
+            constexpr int mm = decltype(mmc)::value;
+            R y0, y1, y2;
+            L.template star<mg0 + mm>(bufX, a, e0, es, p, u, active, y0, y1, y2);
+            yb[(3 * mm + 0) * kYStride + lane] = y0;
+            yb[(3 * mm + 1) * kYStride + lane] = y1;
+            yb[(3 * mm + 2) * kYStride + lane] = y2;
+          });
+          // operands: B = Y (k = 4 kb + l / 16, column l % 16 of tile ct);
+          // A = -Khat rows 16 rt + l % 16 of (mode, direction) k = 4 kb + l / 16
+          float bv[4][nkb];
+          static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
+            constexpr int ct = decltype(ctc)::value;
+#pragma unroll
+            for (int kb = 0; kb < nkb; ++kb) bv[ct][kb] = yb[(4 * kb + lrow) * kYStride + 16 * ct + lcol];
+          });
+          constexpr int base = stp_gen::KhatMfma<N>::off[m0 + mg0];
+          float av[RG][nkb];
+#pragma unroll
+          for (int kb = 0; kb < nkb; ++kb) {
+            // k past the group's 3 gm pairs pads the last k-block: A = 0 there
+            // (the load address is clamped to the group's first pair)
+            const int k = 4 * kb + lrow;
+            const bool live = k < 3 * gm;
+            const int kc = live ? k : 0;
+            const int mm = kc / 3, j = kc - 3 * mm;
+#pragma unroll
+            for (int rt = 0; rt < RG; ++rt) {
+              const float v = ktab[base + mm * (RG * 48) + (rt * 3 + j) * 16 + lcol];
+              av[rt][kb] = live ? v : 0.0f;
+            }
+          }
+          static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
+            constexpr int ct = decltype(ctc)::value;
+            if (ct < nct) {
+              static_for<0, RG>([&](auto rtc) __attribute__((always_inline)) {
+                constexpr int rt = decltype(rtc)::value;
+#pragma unroll
+                for (int kb = 0; kb < nkb; ++kb)
+                  acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt][kb], bv[ct][kb], acc[ct][rt], 0, 0, 0);
+              });
+            }
+          });
+        });
+      }
+    });
+  });
+}
+
 // Float64 residual of the full element system for the current Q (the
 // matrix-free form of eq:stp-lineq after the multiplication with M^-1 S^-1,
 // section "Block-wise back-substitution"):
@@ -916,7 +1271,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
 
 template <>
 hipError_t launch_fused_degree<STP_DEGREE>(const PredictArgs& a, int precision, int refine_steps,
-                                           float* workspace, hipStream_t stream) {
+                                           float* workspace, bool valu_float_chain, hipStream_t stream) {
   constexpr int N = STP_DEGREE;
   using C = Cfg<N>;
   const int64_t groups = (a.n + C::kElems - 1) / C::kElems;
@@ -926,14 +1281,21 @@ hipError_t launch_fused_degree<STP_DEGREE>(const PredictArgs& a, int precision, 
     hipLaunchKernelGGL((fused_solve_kernel<N, double, kInit>), grid, block, 0, stream, a, nullptr);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((fused_solve_kernel<N, float, kInit>), grid, block, 0, stream, a, nullptr);
+  if (valu_float_chain)
+    hipLaunchKernelGGL((fused_solve_kernel<N, float, kInit>), grid, block, 0, stream, a, nullptr);
+  else
+    hipLaunchKernelGGL((mfma_solve_kernel<N, kInit>), grid, block, 0, stream, a, nullptr);
   hipError_t err = hipGetLastError();
   for (int k = 0; k < refine_steps && err == hipSuccess; ++k) {
     hipLaunchKernelGGL((fused_residual_kernel<N>), grid, block, 0, stream, a, workspace);
     err = hipGetLastError();
     if (err != hipSuccess) break;
-    hipLaunchKernelGGL((fused_solve_kernel<N, float, kCorrect>), grid, block, 0, stream, a,
-                       static_cast<const float*>(workspace));
+    if (valu_float_chain)
+      hipLaunchKernelGGL((fused_solve_kernel<N, float, kCorrect>), grid, block, 0, stream, a,
+                         static_cast<const float*>(workspace));
+    else
+      hipLaunchKernelGGL((mfma_solve_kernel<N, kCorrect>), grid, block, 0, stream, a,
+                         static_cast<const float*>(workspace));
     err = hipGetLastError();
   }
   return err;

@@ -3,6 +3,7 @@
 // matrices and FLOP counts.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -70,19 +71,20 @@ stp_status check_common(stp_handle h, int degree, int64_t n, double dt) {
 // Checks one prediction request (everything that needs no device access).
 stp_status check_predict(stp_handle h, int degree, int64_t n, double dt, const double* star, const double* E,
                          const double* Q0, double* Q, stp_precision precision, int refine_steps,
-                         const void* workspace, size_t workspace_bytes, unsigned flags) {
+                         const void* workspace, size_t workspace_bytes, unsigned flags,
+                         bool workspace_checked = true) {
   stp_status st = check_common(h, degree, n, dt);
   if (st != STP_OK) return st;
   if (precision != STP_FP64 && precision != STP_FP32_REFINE) return fail(h, STP_EINVAL, "unknown precision");
   if (refine_steps < 0 || refine_steps > STP_MAX_REFINE)
     return fail(h, STP_EINVAL, "refine_steps must be in 0..3");
-  if (flags & ~STP_FLAG_REFERENCE_KERNEL) return fail(h, STP_EINVAL, "unknown flags");
+  if (flags & ~(STP_FLAG_REFERENCE_KERNEL | STP_FLAG_VALU_FLOAT_CHAIN)) return fail(h, STP_EINVAL, "unknown flags");
   if ((flags & STP_FLAG_REFERENCE_KERNEL) && precision != STP_FP64)
     return fail(h, STP_EINVAL, "the reference kernel is float64 only");
   if (n == 0) return STP_OK;
   if (!star || !E || !Q0 || !Q) return fail(h, STP_EINVAL, "NULL array pointer");
   const size_t need = stp::workspace_bytes(degree, n, static_cast<int>(precision), refine_steps);
-  if (need > 0 && (!workspace || workspace_bytes < need))
+  if (workspace_checked && need > 0 && (!workspace || workspace_bytes < need))
     return fail(h, STP_EWORKSPACE,
                 "workspace of " + std::to_string(need) + " bytes needed, got " + std::to_string(workspace_bytes));
   return STP_OK;
@@ -99,7 +101,8 @@ stp_status launch_predict(stp_handle h, hipStream_t stream, int degree, int64_t 
     err = stp::launch_reference_kernel(degree, a, stream);
   else
     err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps,
-                                   static_cast<float*>(workspace), stream);
+                                   static_cast<float*>(workspace), (flags & STP_FLAG_VALU_FLOAT_CHAIN) != 0,
+                                   stream);
   if (err != hipSuccess) return hip_fail(h, err, "kernel launch");
   return STP_OK;
 }
@@ -128,9 +131,71 @@ stp_status launch_batches(stp_handle h, hipStream_t stream, int n_batches, const
   return STP_OK;
 }
 
+// Device scratch of stp_predict_static: the mixed-precision path's residual
+// buffer lives here instead of in a caller workspace.  In host code `scratch`
+// names a host-side stand-in, never the device array: its device address is
+// taken once per device with hipGetSymbolAddress (each device holds its own
+// copy) and only that address is passed to kernels.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that runs `stream` (the NULL
+// stream: the current device), which must be the current device.
+stp_status scratch_address(stp_handle h, hipStream_t stream, void** out) {
+  int cur = 0;
+  hipError_t err = hipGetDevice(&cur);
+  if (err != hipSuccess) return hip_fail(h, err, "hipGetDevice");
+  if (stream) {
+    hipDevice_t sdev = 0;
+    err = hipStreamGetDevice(stream, &sdev);
+    if (err != hipSuccess) return hip_fail(h, err, "hipStreamGetDevice");
+    if (static_cast<int>(sdev) != cur)
+      return fail(h, STP_EINVAL, "the stream belongs to device " + std::to_string(sdev) + " but device " +
+                                     std::to_string(cur) + " is current");
+  }
+  if (cur < 0 || cur >= kMaxDevices) return fail(h, STP_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[cur]) {
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return hip_fail(h, err, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[cur] = p;
+  }
+  *out = g_scratch_ptr[cur];
+  return STP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t stp_static_scratch_bytes(void) { return kScratchBytes; }
+
+stp_status stp_predict_static(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
+                              const double* star, const double* E, const double* Q0, double* Q, double* Qint,
+                              stp_precision precision, int refine_steps, unsigned flags) {
+  if (!handle) return STP_EINVAL;
+  handle->last_error.clear();
+  const stp_status st = check_predict(handle, degree, n_elements, dt, star, E, Q0, Q, precision, refine_steps,
+                                      nullptr, 0, flags, /*workspace_checked=*/false);
+  if (st != STP_OK) return st;
+  const size_t need = stp::workspace_bytes(degree, n_elements, static_cast<int>(precision), refine_steps);
+  if (need > kScratchBytes)
+    return fail(handle, STP_EWORKSPACE,
+                "stp_predict_static: " + std::to_string(need) + " bytes of scratch needed, at most " +
+                    std::to_string(kScratchBytes) + " available (split the call)");
+  void* ws = nullptr;
+  if (need > 0) {
+    const stp_status sa = scratch_address(handle, static_cast<hipStream_t>(hip_stream), &ws);
+    if (sa != STP_OK) return sa;
+  }
+  return launch_predict(handle, static_cast<hipStream_t>(hip_stream), degree, n_elements, dt, star, E, Q0, Q, Qint,
+                        precision, refine_steps, ws, flags);
+}
 
 stp_status stp_create(stp_handle* handle) {
   if (!handle) return STP_EINVAL;

@@ -18,7 +18,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 def _declared_symbols():
     txt = open(os.path.join(ROOT, "include", "stp.h")).read()
-    return sorted(set(re.findall(r"^(?:stp_status|const char\*)\s+(stp_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:stp_status|const char\*|size_t)\s+(stp_\w+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -64,6 +64,34 @@ def test_argument_validation_without_device():
     assert h.lib.stp_validate(h.ptr, None, 3, 0, 1e-3, None, None, None) == 0
     assert h.lib.stp_validate(h.ptr, None, 3, 1, 1e-3, None, None, None) == -1
     assert h.lib.stp_create(None) == -1
+    h.close()
+
+
+def test_static_predict_argument_checks_without_device():
+    """stp_predict_static: the host checks of stp_predict, and a call needing
+    more scratch than the library's array is refused before any device work
+    (the size check comes before the device address is looked up)."""
+    h = _lib.Handle()
+    lib = h.lib
+    p = ctypes.c_void_p(1)
+    cap = lib.stp_static_scratch_bytes()
+    assert cap == 256 << 20
+
+    def call(degree=6, n=1, prec=1, refine=1, flags=0, dt=1e-3, ptr=p):
+        return lib.stp_predict_static(h.ptr, None, degree, n, dt, ptr, ptr, ptr, ptr, ptr, prec, refine, flags)
+
+    assert call(degree=8) == -2
+    assert call(n=-1) == -1
+    assert call(dt=0.0) == -1
+    assert call(refine=4) == -1
+    assert call(flags=8) == -1
+    assert call(ptr=ctypes.c_void_p(0)) == -1
+    assert call(n=0, ptr=ctypes.c_void_p(0)) == 0
+    per_el = 13 * 84 * 7 * 4
+    too_many = cap // per_el + 1
+    assert call(n=too_many) == -7
+    assert "scratch" in lib.stp_last_error(h.ptr).decode()
+    assert lib.stp_predict_static(None, None, 6, 1, 1e-3, p, p, p, p, p, 0, 0, 0) == -1
     h.close()
 
 

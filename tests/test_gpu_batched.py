@@ -34,29 +34,38 @@ def _batches(ws):
 
 @pytest.fixture(scope="module")
 def lts_small():
-    return wl.make_lts(80, seed=9)
+    """Four rate-2 clusters x degrees 3..6 (16 batches, 60 launches per
+    cycle), 32 elements: 4, 2, 1, 1 per degree in clusters 0..3."""
+    return wl.make_lts(32, seed=9, shares=(0.5, 0.25, 0.125, 0.125))
 
 
 _ORACLE = {}
 
 
-def _oracle(w):
-    """Oracle of every element of a batch (cached per batch)."""
-    if w.name not in _ORACLE:
-        _ORACLE[w.name] = opool.solve_many(w.N, w.star, w.E, w.Q0, w.dt)
-    return _ORACLE[w.name]
+def _oracle_all(batches):
+    """Oracle of every element of every batch, in one worker pool (cached)."""
+    missing = [w for w in batches if w.name not in _ORACLE]
+    if missing:
+        jobs = [(w.N, w.star[e], w.E[e], w.Q0[e], w.dt) for w in missing for e in range(w.n)]
+        _say(f"  oracle on all {len(jobs)} elements of {len(missing)} batches")
+        res = opool.solve_jobs(jobs, progress=opool._print_progress)
+        k = 0
+        for w in missing:
+            _ORACLE[w.name] = (np.stack([r[0] for r in res[k:k + w.n]]), np.stack([r[1] for r in res[k:k + w.n]]))
+            k += w.n
+    return [_ORACLE[w.name] for w in batches]
 
 
 @pytest.mark.parametrize("precision,refine", [("fp64", 0), ("fp32_refine", 2)])
 def test_batched_equals_single_calls_and_oracle(lts_small, precision, refine):
     _say(f"[gpu] batched LTS {len(lts_small)} batches precision={precision}")
+    oracles = _oracle_all(lts_small)
     bs = api.predict_batched(_batches(lts_small), precision=precision, refine_steps=refine)
     torch.cuda.synchronize()
-    for w, b in zip(lts_small, bs):
+    for w, b, (Xo, Io) in zip(lts_small, bs, oracles):
         Q1, I1 = api.predict(b["Q0"], b["star"], b["E"], w.dt, w.N, precision=precision, refine_steps=refine)
         torch.cuda.synchronize()
         assert torch.equal(b["Q"], Q1) and torch.equal(b["Qint"], I1), w.name
-        Xo, Io = _oracle(w)
         _say(f"  {w.name} n={w.n} dt={w.dt:.3e}: every element")
         parity.check(b["Q"].cpu().numpy(), Xo, TOL, "Q", say=_say)
         parity.check(b["Qint"].cpu().numpy(), Io, TOL, "Qint", say=_say)
