@@ -41,14 +41,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_flops(N: int, khat_nnz: int, star_nnz: int = 54, g_nnz: int = 3) -> int:
+def algorithmic_flops(N: int, khat_nnz: int, star_nnz: int = 54, g_nnz: int = 3, nq: int = 13) -> int:
     """FLOP per element that Algorithm 3 cannot avoid: RHS initialisation,
     dark-blue T x T solves, G couplings, star products with the non-zeros of
-    the poroelastic star matrices (54 per direction) for every mode above
-    degree 0, and the non-zero Khat entries (the sparsity-aware count)."""
+    the star matrices (54 per direction for the poroelastic system) for every
+    mode above degree 0, and the non-zero Khat entries (the sparsity-aware
+    count)."""
     B, T = wl.n_modes(N), N + 1
-    return (13 * B * T + 2 * 13 * T * T * B + 2 * T * B * g_nnz + 2 * 3 * star_nnz * T * (B - 1)
-            + 2 * 13 * T * khat_nnz)
+    return (nq * B * T + 2 * nq * T * T * B + 2 * T * B * g_nnz + 2 * 3 * star_nnz * T * (B - 1)
+            + 2 * nq * T * khat_nnz)
 
 
 def dense_block_flops(N: int) -> int:
@@ -59,11 +60,11 @@ def dense_block_flops(N: int) -> int:
             + 2 * 13 * T * 3 * up)
 
 
-def hbm_bytes(N: int) -> int:
+def hbm_bytes(N: int, nq: int = 13) -> int:
     """Compulsory HBM bytes per element of one float64 call: read Q0, star, E;
     write Q and Qint."""
     B, T = wl.n_modes(N), N + 1
-    return 8 * (13 * B + 3 * 169 + 169 + 13 * B * T + 13 * B)
+    return 8 * (nq * B + 4 * nq * nq + nq * B * T + nq * B)
 
 
 # ---------------------------------------------------------------------------
@@ -96,8 +97,9 @@ def cpu_baseline(w, ids, procs):
 def time_path(torch, api, dev, w, steps, warmup, **kw):
     """Warm up, then time `steps` calls with HIP events on torch's current
     stream (the stream the library launches on)."""
-    Q = torch.empty((w.n, 13, wl.n_modes(w.N), w.N + 1), dtype=torch.float64, device="cuda")
-    Qi = torch.empty((w.n, 13, wl.n_modes(w.N)), dtype=torch.float64, device="cuda")
+    nq = w.Q0.shape[1]
+    Q = torch.empty((w.n, nq, wl.n_modes(w.N), w.N + 1), dtype=torch.float64, device="cuda")
+    Qi = torch.empty((w.n, nq, wl.n_modes(w.N)), dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         api.predict(dev["Q0"], dev["star"], dev["E"], w.dt, w.N, Q=Q, Qint=Qi, **kw)
     torch.cuda.synchronize()
@@ -172,12 +174,18 @@ def run_lts(args):
         nnz = sum(int((Kh[:, :wl.n_modes(g - 1), wl.n_modes(g - 1):wl.n_modes(g)] != 0).sum())
                   for g in range(1, N + 1))
         flops += algorithmic_flops(N, nnz) * batches[i].n
+    stages = wl.lts_stages(batches)
     paths = {}
-    for name, kw in (("fp64", dict(precision="fp64", refine_steps=0)),
-                     ("fp32_refine", dict(precision="fp32_refine", refine_steps=args.refine_steps))):
+    for name, kw, staged in (("fp64", dict(precision="fp64", refine_steps=0), True),
+                             ("fp64_serial_graph", dict(precision="fp64", refine_steps=0), False),
+                             ("fp32_refine", dict(precision="fp32_refine", refine_steps=args.refine_steps), True)):
         if name == "fp32_refine" and args.skip_fp32:
             continue
-        g = api.Graph([dev[i] for i in cyc], **kw)
+        if staged:
+            # the batches of one sub-step on parallel graph branches
+            g = api.Graph([dev[i] for st in stages for i in st], stages=[len(st) for st in stages], **kw)
+        else:
+            g = api.Graph([dev[i] for i in cyc], **kw)
         for _ in range(args.warmup):
             g.launch()
         torch.cuda.synchronize()
@@ -191,7 +199,8 @@ def run_lts(args):
         err = None
         if oracle:
             err = max(float(rel_l2(dev[i]["Q"][:1].cpu().numpy(), oracle[i][None])[0]) for i in oracle)
-        paths[name] = dict(ms_per_cycle=ms, el_per_s=updates / (ms * 1e-3), max_rel_l2=err, **kw)
+        paths[name] = dict(ms_per_cycle=ms, el_per_s=updates / (ms * 1e-3), max_rel_l2=err,
+                           graph="staged (parallel branches per sub-step)" if staged else "serial", **kw)
         log(f"[bench] LTS {name}: {ms:.3f} ms per cycle, {updates / ms / 1e3:.3f} M el/s, max rel L2 {err}")
         g.close()
     p = paths["fp64"]
@@ -203,6 +212,7 @@ def run_lts(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded heterogeneous poroelastic materials, random tetrahedra, Q0 ~ N(0,1))",
         "config": {"workload": args.workload, "batches": len(batches), "launches_per_cycle": len(cyc),
+                   "stages_per_cycle": len(stages),
                    "elements": sum(b.n for b in batches), "updates_per_cycle": updates,
                    "clusters": {str(k): sum(b.n for b in batches if b.meta["cluster"] == k)
                                 for k in sorted({b.meta["cluster"] for b in batches})},
@@ -228,7 +238,8 @@ def parity_report(X, Xo):
     el = float(rel_l2(X, Xo).max())
     ax = tuple(range(2, X.ndim))
     pq = (np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))).max(axis=0)
-    return dict(max_rel_l2=el, max_rel_l2_per_quantity=dict(zip(wl.QUANTITIES, map(float, pq))),
+    names = wl.QUANTITIES if X.shape[1] == 13 else wl.MAXWELL_QUANTITIES
+    return dict(max_rel_l2=el, max_rel_l2_per_quantity=dict(zip(names, map(float, pq))),
                 max_rel_l2_worst_quantity=float(pq.max()))
 
 
@@ -320,6 +331,19 @@ def mixed_leg(args, torch, api, name):
         log(f"[bench] {name} fp32+{K}: {rec['el_per_s'] / 1e6:.3f} M el/s, call {tk['call_ms_mean']:.2f} ms, "
             f"rel L2 element {rep['max_rel_l2']:.2e} worst quantity {rep['max_rel_l2_worst_quantity']:.2e}, "
             f"frac of composite bound {rec['roofline']['frac']:.3f}")
+    # the same chain with its green update on the matrix cores (kept for comparison)
+    out["mfma_float_chain"] = {}
+    for K in (0, args.refine_steps):
+        steps = max(3, min(args.steps, 10))
+        tk, Q, Qi = time_path(torch, api, dev, w, steps, min(args.warmup, 3), precision="fp32_refine",
+                              refine_steps=K, mfma_float_chain=True)
+        rep = parity_report(Q[ids].cpu().numpy(), Xo)
+        del Q, Qi
+        torch.cuda.empty_cache()
+        out["mfma_float_chain"][str(K)] = dict(tk, timed_calls=steps, el_per_s=w.n / (tk["call_ms_mean"] * 1e-3),
+                                               **rep)
+        log(f"[bench] {name} fp32+{K} matrix-core chain: {w.n / tk['call_ms_mean'] / 1e3:.3f} M el/s, "
+            f"call {tk['call_ms_mean']:.2f} ms, worst quantity {rep['max_rel_l2_worst_quantity']:.2e}")
     t64, Q, Qi = time_path(torch, api, dev, w, max(3, min(args.steps, 10)), min(args.warmup, 3),
                            precision="fp64")
     rep = parity_report(Q[ids].cpu().numpy(), Xo)
@@ -371,7 +395,9 @@ def main():
         return
     log(f"[bench] generating workload {args.workload}")
     t = time.perf_counter()
-    w = wl.make_workload(args.workload)
+    maxwell = args.workload in wl.MAXWELL_CONFIGS
+    w = wl.make_maxwell_workload(args.workload) if maxwell else wl.make_workload(args.workload)
+    nq = w.Q0.shape[1]
     log(f"[bench] generated n={w.n} N={w.N} dt={w.dt:.4e} in {time.perf_counter() - t:.1f}s")
     sample = wl.oracle_sample(w.n)
 
@@ -404,10 +430,13 @@ def main():
     torch.cuda.synchronize()
 
     nnz = khat_nnz(api, w.N)
-    F_alg = algorithmic_flops(w.N, nnz)
-    F_dense = dense_block_flops(w.N)
-    F_paper, F_exec = api.flops(w.N)
-    bytes_el = hbm_bytes(w.N)
+    # non-zeros per direction of the star matrices (54 poroelastic, 12 Maxwell)
+    star_nnz = int((np.abs(w.star[:64]) != 0).sum(axis=(2, 3)).max())
+    g_nnz = int((np.triu(w.E[:64], 1) != 0).sum(axis=(1, 2)).max())
+    F_alg = algorithmic_flops(w.N, nnz, star_nnz, g_nnz, nq)
+    F_dense = dense_block_flops(w.N) if nq == 13 else None
+    F_paper, F_exec = api.flops(w.N) if nq == 13 else (None, None)
+    bytes_el = hbm_bytes(w.N, nq)
 
     paths = {}
     log("[bench] fp64 path")
@@ -419,9 +448,22 @@ def main():
     paths["fp64"] = dict(t64, el_per_s=w.n / (t64["ms_per_step"] * 1e-3), **rep64)
     log(f"[bench] fp64 {paths['fp64']['el_per_s'] / 1e6:.3f} M el/s, call {t64['call_ms_mean']:.3f} ms,"
         f" {rep64}")
+    dev_keep = dev if maxwell else None
     del Q, Qi, dev
     torch.cuda.empty_cache()
-    if not args.skip_fp32 and args.mixed_workload != "none":
+    if maxwell:
+        log("[bench] fp32 + 1 refinement step on the same inputs")
+        t32, Q, Qi = time_path(torch, api, dev_keep, w, args.steps, args.warmup, precision="fp32_refine",
+                               refine_steps=args.refine_steps)
+        rep32 = {}
+        if oracle:
+            ids = list(oracle)
+            rep32 = parity_report(Q[ids].cpu().numpy(), np.stack([oracle[i][0] for i in ids]))
+        paths["fp32_refine"] = dict(t32, refine_steps=args.refine_steps,
+                                    el_per_s=w.n / (t32["call_ms_mean"] * 1e-3), **rep32)
+        del Q, Qi, dev_keep
+        torch.cuda.empty_cache()
+    elif not args.skip_fp32 and args.mixed_workload != "none":
         try:
             paths["fp32_refine"] = mixed_leg(args, torch, api, args.mixed_workload)
         except Exception as exc:  # reported, never silently replaced
@@ -445,8 +487,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded heterogeneous poroelastic materials, random tetrahedra, Q0 ~ N(0,1))",
-        "config": {"workload": w.name, "degree": w.N, "elements": w.n,
-                   "unknowns_per_element": 13 * wl.n_modes(w.N) * (w.N + 1), "dt": w.dt},
+        "config": {"workload": w.name, "degree": w.N, "elements": w.n, "quantities": int(nq),
+                   "unknowns_per_element": int(nq) * wl.n_modes(w.N) * (w.N + 1), "dt": w.dt},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
                      "measured_peak": peaks["fp64_valu_tflops"],

@@ -87,10 +87,14 @@ typedef enum stp_precision {
  * the fused register-resident kernel.  Same results up to rounding; kept
  * as an independent GPU implementation and for debugging. */
 #define STP_FLAG_REFERENCE_KERNEL 1u
-/* STP_FP32_REFINE only: run the float32 chain's green-block update on the
- * vector ALU instead of the matrix cores (same results up to float32
- * rounding; kept to compare the two). */
-#define STP_FLAG_VALU_FLOAT_CHAIN 2u
+/* STP_FP32_REFINE only: run the float32 chain's green-block update (the
+ * star x stiffness x time products, Algorithm 3) on the matrix cores,
+ * v_mfma_f32_16x16x4f32 with float32 accumulation, instead of as sparse
+ * fused multiply-adds on the vector ALU.  Same results up to float32
+ * rounding.  The dense 16 x 16 x 4 tiles execute ~3x the non-zero products
+ * of the sparse update at twice the vector rate, so on MI355X this variant
+ * is slower; it is kept selectable for comparison. */
+#define STP_FLAG_MFMA_FLOAT_CHAIN 2u
 
 /* Create / destroy a handle.  No device work is done by either. */
 stp_status stp_create(stp_handle* handle);
@@ -152,6 +156,32 @@ stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z,
  * "tab:flop-count"), and the count this library executes in its fused
  * float64 kernel (useful FLOP: dense star matrices, non-zero Khat entries). */
 stp_status stp_flops(int degree, double* paper_bound, double* executed);
+
+/* ---- Other systems with a stiff upper-triangular source -------------------
+ *
+ * Algorithm 3 needs only that E is upper triangular; the Jacobians are data
+ * (section "Other applications").  These entry points take the quantity
+ * count nq of the system; the kernels are compiled for nq = STP_NQ (13, the
+ * poroelastic system) and nq = STP_NQ_MAXWELL (6: the damped Maxwell
+ * equations, quantities (Ex, Ey, Ez, Hx, Hy, Hz), source -sigma/eps on the
+ * electric field); any other nq returns STP_EINVAL.  Arrays as for
+ * stp_predict with 13 replaced by nq: star [n][3][nq][nq], E [n][nq][nq],
+ * Q0 [n][nq][B], Q [n][nq][B][T], Qint [n][nq][B].  With nq = 13 these are
+ * exactly stp_workspace_size / stp_predict / stp_validate.  The reference
+ * kernel (STP_FLAG_REFERENCE_KERNEL) is for nq = 13 only. */
+#define STP_NQ_MAXWELL 6
+stp_status stp_workspace_size_nq(stp_handle handle, int n_quantities, int degree,
+                                 int64_t n_elements, stp_precision precision,
+                                 int refine_steps, size_t* bytes);
+stp_status stp_predict_nq(stp_handle handle, void* hip_stream, int n_quantities,
+                          int degree, int64_t n_elements, double dt,
+                          const double* star, const double* E, const double* Q0,
+                          double* Q, double* Qint, stp_precision precision,
+                          int refine_steps, void* workspace, size_t workspace_bytes,
+                          unsigned flags);
+stp_status stp_validate_nq(stp_handle handle, void* hip_stream, int n_quantities,
+                           int degree, int64_t n_elements, double dt,
+                           const double* star, const double* E, const double* Q0);
 
 /* ---- Prediction without a caller workspace --------------------------------
  *
@@ -230,6 +260,26 @@ stp_status stp_graph_create(stp_handle handle, void* hip_stream, int n_batches, 
  * synchronise. */
 stp_status stp_graph_launch(stp_graph graph, void* hip_stream);
 stp_status stp_graph_destroy(stp_graph graph);
+
+/* Concurrent batches.  In a cycle of clustered local time stepping the
+ * batches predicted at one sub-step (one per cluster due and degree) are
+ * independent of each other.  batches[0 .. sum(stage_sizes)) are split into
+ * n_stages consecutive stages of stage_sizes[s] batches: the batches of one
+ * stage must write distinct outputs (inputs may be shared) and are captured
+ * on parallel graph branches (up to 4 streams of default priority, batches
+ * assigned round robin); each stage starts after the previous one has
+ * completed.  Concurrent STP_FP32_REFINE batches need their own residual
+ * buffers: the workspace is the largest sum over one stage of the batches'
+ * stp_workspace_size (each rounded up to 256 bytes), as
+ * stp_staged_workspace_size returns.  Otherwise as stp_graph_create; the
+ * graph is launched and destroyed with stp_graph_launch / stp_graph_destroy. */
+stp_status stp_staged_workspace_size(stp_handle handle, int n_stages, const int* stage_sizes,
+                                     const stp_batch* batches, stp_precision precision,
+                                     int refine_steps, size_t* bytes);
+stp_status stp_graph_create_staged(stp_handle handle, void* hip_stream, int n_stages,
+                                   const int* stage_sizes, const stp_batch* batches,
+                                   stp_precision precision, int refine_steps, void* workspace,
+                                   size_t workspace_bytes, unsigned flags, stp_graph* graph);
 
 /* ---- Machine ceilings ----------------------------------------------------
  *

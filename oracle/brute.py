@@ -69,7 +69,7 @@ def tet_quadrature(n):
 def assemble_brute(N, star, E, Q0, dt, nq_space=None, nq_time=None):
     """Unequilibrated dense (Y, r) of eq:stp for one element, tiny N only."""
     modes = _mode_list(N)
-    B, T, NQ = len(modes), N + 1, 13
+    B, T, NQ = len(modes), N + 1, np.asarray(E).shape[0]
     nq_space = nq_space or (N + 3)
     nq_time = nq_time or (N + 2)
     x, y, z, ws = tet_quadrature(nq_space)

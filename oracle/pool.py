@@ -88,8 +88,9 @@ def solve_many(N: int, star, E, Q0, dt: float, procs: int | None = None, progres
     star = np.asarray(star); E = np.asarray(E); Q0 = np.asarray(Q0)
     n = star.shape[0]
     B = basis.n_modes(N)
-    X = np.empty((n, 13, B, N + 1))
-    Qi = np.empty((n, 13, B))
+    nq = E.shape[-1]
+    X = np.empty((n, nq, B, N + 1))
+    Qi = np.empty((n, nq, B))
     res = solve_jobs([(N, star[e], E[e], Q0[e], dt) for e in range(n)], procs, progress)
     for e, (x, q) in enumerate(res):
         X[e], Qi[e] = x, q

@@ -41,7 +41,7 @@ import scipy.linalg as sla
 
 from . import basis
 
-NQ = 13
+NQ = 13   # quantities of the poroelastic system; other systems pass their own (shape of E)
 
 
 @lru_cache(maxsize=None)
@@ -55,7 +55,8 @@ def reference_operators(N: int):
 
 
 def _balance(Astar, Estar):
-    """Power-of-two diagonal D (length 13) balancing sum_j |A^{j*}| + |E*|."""
+    """Power-of-two diagonal D (one entry per quantity) balancing
+    sum_j |A^{j*}| + |E*|."""
     Mabs = np.abs(Astar).sum(axis=0) + np.abs(Estar)
     _, (scale, _perm) = sla.matrix_balance(Mabs, permute=False, separate=True)
     return scale
@@ -63,7 +64,9 @@ def _balance(Astar, Estar):
 
 def assemble(N: int, star: np.ndarray, E: np.ndarray, Q0: np.ndarray, dt: float,
              equilibrate: bool = True):
-    """Dense (Y, r, D) for one element.  star: (3,13,13), E: (13,13), Q0: (13,B).
+    """Dense (Y, r, D) for one element.  star: (3,nq,nq), E: (nq,nq), Q0: (nq,B);
+    nq = 13 for the poroelastic system, any other for the systems of section
+    "Other applications" (same definition, another quantity count).
 
     Y and r are of the equilibrated system when ``equilibrate``; the
     physical solution is X = D x with x = Y^-1 r (quantity-wise scaling).
@@ -72,13 +75,13 @@ def assemble(N: int, star: np.ndarray, E: np.ndarray, Q0: np.ndarray, dt: float,
     B, T = M.shape[0], N + 1
     Astar = dt * np.asarray(star, dtype=np.float64)
     Estar = dt * np.asarray(E, dtype=np.float64)
-    D = _balance(Astar, Estar) if equilibrate else np.ones(NQ)
+    nq = Estar.shape[0]
+    D = _balance(Astar, Estar) if equilibrate else np.ones(nq)
     Dinv = 1.0 / D
     Ap = Dinv[None, :, None] * Astar * D[None, None, :]
     Ep = Dinv[:, None] * Estar * D[None, :]
     Q0p = Dinv[:, None] * np.asarray(Q0, dtype=np.float64)
-    I13 = np.eye(NQ)
-    Y = np.kron(I13, np.kron(M, W - Kt))
+    Y = np.kron(np.eye(nq), np.kron(M, W - Kt))
     Y -= np.kron(Ep, np.kron(M, S))
     for j in range(3):
         Y += np.kron(Ap[j], np.kron(K[j], S))
@@ -89,7 +92,7 @@ def assemble(N: int, star: np.ndarray, E: np.ndarray, Q0: np.ndarray, dt: float,
 
 def solve_element(N: int, star, E, Q0, dt, equilibrate: bool = True, return_residual=False,
                   refine: bool = True):
-    """Space-time DOFs X (13, B, N+1) and time-integrated DOFs (13, B)."""
+    """Space-time DOFs X (nq, B, N+1) and time-integrated DOFs (nq, B)."""
     Y, r, D = assemble(N, star, E, Q0, dt, equilibrate)
     lu = sla.lu_factor(Y, overwrite_a=False, check_finite=True)
     x = sla.lu_solve(lu, r)
@@ -103,7 +106,8 @@ def solve_element(N: int, star, E, Q0, dt, equilibrate: bool = True, return_resi
             if np.linalg.norm(dx) <= 1e-17 * np.linalg.norm(x):
                 break
     B, T = basis.n_modes(N), N + 1
-    X = (D[:, None] * x.reshape(NQ, B * T)).reshape(NQ, B, T)
+    nq = len(D)
+    X = (D[:, None] * x.reshape(nq, B * T)).reshape(nq, B, T)
     _, _, _, _, _, _, chi_int = reference_operators(N)
     Qint = dt * np.einsum("pls,s->pl", X, chi_int)
     if return_residual:
@@ -119,8 +123,9 @@ def solve(N: int, star, E, Q0, dt, equilibrate: bool = True, refine: bool = True
     star = np.asarray(star); E = np.asarray(E); Q0 = np.asarray(Q0)
     n = star.shape[0]
     B = basis.n_modes(N)
-    X = np.empty((n, NQ, B, N + 1))
-    Qi = np.empty((n, NQ, B))
+    nq = E.shape[-1]
+    X = np.empty((n, nq, B, N + 1))
+    Qi = np.empty((n, nq, B))
     for e in range(n):
         X[e], Qi[e] = solve_element(N, star[e], E[e], Q0[e], dt, equilibrate, refine=refine)
     return X, Qi

@@ -19,11 +19,14 @@ STATUS_NAMES = {0: "STP_OK", -1: "STP_EINVAL", -2: "STP_EDEGREE", -3: "STP_ENOTU
 STP_FP64 = 0
 STP_FP32_REFINE = 1
 STP_FLAG_REFERENCE_KERNEL = 1
+STP_FLAG_MFMA_FLOAT_CHAIN = 2
 MAX_DEGREE = 7
 EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "stp_validate",
             "stp_reference_matrices", "stp_flops", "stp_batched_workspace_size",
             "stp_predict_batched", "stp_graph_create", "stp_graph_launch", "stp_graph_destroy",
             "stp_measure_peaks", "stp_static_scratch_bytes", "stp_predict_static",
+            "stp_staged_workspace_size", "stp_graph_create_staged",
+            "stp_workspace_size_nq", "stp_predict_nq", "stp_validate_nq",
             "stp_status_string", "stp_last_error")
 
 
@@ -68,6 +71,11 @@ def load(path: str = LIB_PATH):
     lib.stp_predict.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
                                 ctypes.c_int, ctypes.c_int, vp, sz, ctypes.c_uint]
     lib.stp_validate.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp]
+    lib.stp_workspace_size_nq.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(sz)]
+    lib.stp_predict_nq.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
+                                   ctypes.c_int, ctypes.c_int, vp, sz, ctypes.c_uint]
+    lib.stp_validate_nq.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64, dbl, vp, vp, vp]
     lib.stp_static_scratch_bytes.argtypes = []
     lib.stp_static_scratch_bytes.restype = sz
     lib.stp_predict_static.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
@@ -81,6 +89,10 @@ def load(path: str = LIB_PATH):
                                         ctypes.c_uint]
     lib.stp_graph_create.argtypes = [vp, vp, ctypes.c_int, pb, ctypes.c_int, ctypes.c_int, vp, sz,
                                      ctypes.c_uint, ctypes.POINTER(vp)]
+    lib.stp_staged_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), pb, ctypes.c_int,
+                                              ctypes.c_int, ctypes.POINTER(sz)]
+    lib.stp_graph_create_staged.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), pb, ctypes.c_int,
+                                            ctypes.c_int, vp, sz, ctypes.c_uint, ctypes.POINTER(vp)]
     lib.stp_graph_launch.argtypes = [vp, vp]
     lib.stp_graph_destroy.argtypes = [vp]
     lib.stp_measure_peaks.argtypes = [vp, vp, vp, sz, ctypes.POINTER(StpPeaks)]

@@ -28,38 +28,43 @@ def _ptr(t):
 _PREC = {"fp64": _lib.STP_FP64, "fp32_refine": _lib.STP_FP32_REFINE}
 
 
-def workspace_size(degree: int, n: int, precision: str = "fp64", refine_steps: int = 1) -> int:
+def workspace_size(degree: int, n: int, precision: str = "fp64", refine_steps: int = 1, nq: int = 13) -> int:
     h = _h()
     out = ctypes.c_size_t()
-    h.check(h.lib.stp_workspace_size(h.ptr, degree, n, _PREC[precision], refine_steps,
-                                     ctypes.byref(out)))
+    h.check(h.lib.stp_workspace_size_nq(h.ptr, nq, degree, n, _PREC[precision], refine_steps,
+                                        ctypes.byref(out)))
     return out.value
 
 
 def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine_steps: int = 1,
             Q=None, Qint=None, with_qint: bool = True, reference_kernel: bool = False,
-            stream=None):
-    """Space-time DOFs Q [n,13,B,T] and time-integrated DOFs Qint [n,13,B].
+            stream=None, mfma_float_chain: bool = False):
+    """Space-time DOFs Q [n,nq,B,T] and time-integrated DOFs Qint [n,nq,B].
 
-    Q0 [n,13,B], star [n,3,13,13], E [n,13,13]: float64, contiguous, on the
-    same cuda device.  Outputs are allocated here unless passed in.  The call
-    is asynchronous on ``stream`` (default: torch's current stream)."""
+    Q0 [n,nq,B], star [n,3,nq,nq], E [n,nq,nq]: float64, contiguous, on the
+    same cuda device; nq = 13 (poroelastic) or 6 (damped Maxwell), taken
+    from Q0 (stp_predict_nq).  Outputs are allocated here unless passed in.  The call
+    is asynchronous on ``stream`` (default: torch's current stream).
+    ``mfma_float_chain`` selects the matrix-core float32 chain
+    (STP_FLAG_MFMA_FLOAT_CHAIN) for precision="fp32_refine"."""
     import torch
     h = _h()
     n = _check_inputs(Q0, star, E, degree)
+    nq = int(Q0.shape[1])
     B, T = n_modes(degree), degree + 1
     if Q is None:
-        Q = torch.empty((n, 13, B, T), dtype=torch.float64, device=Q0.device)
+        Q = torch.empty((n, nq, B, T), dtype=torch.float64, device=Q0.device)
     if Qint is None and with_qint:
-        Qint = torch.empty((n, 13, B), dtype=torch.float64, device=Q0.device)
-    ws = workspace_size(degree, n, precision, refine_steps)
+        Qint = torch.empty((n, nq, B), dtype=torch.float64, device=Q0.device)
+    ws = workspace_size(degree, n, precision, refine_steps, nq)
     work = torch.empty(ws, dtype=torch.uint8, device=Q0.device) if ws else None
     if stream is None:
         stream = torch.cuda.current_stream(Q0.device)
-    flags = _lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0
-    h.check(h.lib.stp_predict(h.ptr, ctypes.c_void_p(stream.cuda_stream), degree, n, float(dt),
-                              _ptr(star), _ptr(E), _ptr(Q0), _ptr(Q), _ptr(Qint), _PREC[precision],
-                              refine_steps, _ptr(work), ws, flags))
+    flags = (_lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0) | \
+        (_lib.STP_FLAG_MFMA_FLOAT_CHAIN if mfma_float_chain else 0)
+    h.check(h.lib.stp_predict_nq(h.ptr, ctypes.c_void_p(stream.cuda_stream), nq, degree, n, float(dt),
+                                 _ptr(star), _ptr(E), _ptr(Q0), _ptr(Q), _ptr(Qint), _PREC[precision],
+                                 refine_steps, _ptr(work), ws, flags))
     return Q, Qint
 
 
@@ -88,8 +93,9 @@ def predict_static(Q0, star, E, dt: float, degree: int, Q, Qint=None, precision:
 def _check_inputs(Q0, star, E, degree):
     import torch
     n = int(Q0.shape[0])
+    nq = int(Q0.shape[1]) if Q0.dim() == 3 else 13
     B = n_modes(degree)
-    for name, t, shape in (("Q0", Q0, (n, 13, B)), ("star", star, (n, 3, 13, 13)), ("E", E, (n, 13, 13))):
+    for name, t, shape in (("Q0", Q0, (n, nq, B)), ("star", star, (n, 3, nq, nq)), ("E", E, (n, nq, nq))):
         if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
             raise ValueError(f"{name}: expected contiguous cuda float64 {shape}, got "
                              f"{tuple(t.shape)} {t.dtype} cuda={t.is_cuda}")
@@ -106,6 +112,8 @@ def _batch_array(batches, with_qint=True):
     for i, b in enumerate(batches):
         N = int(b["degree"])
         n = _check_inputs(b["Q0"], b["star"], b["E"], N)
+        if b["Q0"].shape[1] != 13:
+            raise ValueError("batched calls and graphs take the 13-quantity system")
         if b.get("Q") is None:
             b["Q"] = torch.empty((n, 13, n_modes(N), N + 1), dtype=torch.float64, device=b["Q0"].device)
         if b.get("Qint") is None and with_qint:
@@ -150,24 +158,39 @@ class Graph:
     """stp_graph_create / stp_graph_launch / stp_graph_destroy: the launches
     of one stp_predict_batched call captured once on ``capture_stream`` (a
     non-default torch stream; a new one if None) and replayed by launch().
-    Keeps the batches' tensors and the workspace alive."""
+    With ``stages`` (list of batch counts, summing to len(batches)),
+    stp_graph_create_staged: the batches of one stage run on parallel graph
+    branches.  Keeps the batches' tensors and the workspace alive."""
 
     def __init__(self, batches, precision: str = "fp64", refine_steps: int = 1, with_qint: bool = True,
-                 reference_kernel: bool = False, capture_stream=None):
+                 reference_kernel: bool = False, capture_stream=None, stages=None):
         import torch
         self._h = _h()
         self.batches = batches
         self._arr = _batch_array(batches, with_qint)
         dev = batches[0]["Q0"].device if batches else torch.device("cuda")
-        self._work = _batched_workspace(self._arr, len(batches), precision, refine_steps, dev)
-        self._stream = capture_stream if capture_stream is not None else torch.cuda.Stream(dev)
         flags = _lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0
         self.ptr = ctypes.c_void_p()
-        torch.cuda.current_stream(dev).synchronize()
-        self._h.check(self._h.lib.stp_graph_create(
-            self._h.ptr, ctypes.c_void_p(self._stream.cuda_stream), len(batches), self._arr,
-            _PREC[precision], refine_steps, _ptr(self._work),
-            self._work.numel() if self._work is not None else 0, flags, ctypes.byref(self.ptr)))
+        self._stream = capture_stream if capture_stream is not None else torch.cuda.Stream(dev)
+        if stages is None:
+            self._work = _batched_workspace(self._arr, len(batches), precision, refine_steps, dev)
+            torch.cuda.current_stream(dev).synchronize()
+            self._h.check(self._h.lib.stp_graph_create(
+                self._h.ptr, ctypes.c_void_p(self._stream.cuda_stream), len(batches), self._arr,
+                _PREC[precision], refine_steps, _ptr(self._work),
+                self._work.numel() if self._work is not None else 0, flags, ctypes.byref(self.ptr)))
+        else:
+            if sum(stages) != len(batches):
+                raise ValueError("stages must sum to the number of batches")
+            self._stages = (ctypes.c_int * max(len(stages), 1))(*stages)
+            out = ctypes.c_size_t()
+            self._h.check(self._h.lib.stp_staged_workspace_size(self._h.ptr, len(stages), self._stages, self._arr,
+                                                                _PREC[precision], refine_steps, ctypes.byref(out)))
+            self._work = torch.empty(out.value, dtype=torch.uint8, device=dev) if out.value else None
+            torch.cuda.current_stream(dev).synchronize()
+            self._h.check(self._h.lib.stp_graph_create_staged(
+                self._h.ptr, ctypes.c_void_p(self._stream.cuda_stream), len(stages), self._stages, self._arr,
+                _PREC[precision], refine_steps, _ptr(self._work), out.value, flags, ctypes.byref(self.ptr)))
 
     def launch(self, stream=None):
         import torch
@@ -210,8 +233,8 @@ def validate(Q0, star, E, dt: float, degree: int, stream=None) -> None:
     h = _h()
     if stream is None:
         stream = torch.cuda.current_stream(Q0.device)
-    h.check(h.lib.stp_validate(h.ptr, ctypes.c_void_p(stream.cuda_stream), degree, int(Q0.shape[0]),
-                               float(dt), _ptr(star), _ptr(E), _ptr(Q0)))
+    h.check(h.lib.stp_validate_nq(h.ptr, ctypes.c_void_p(stream.cuda_stream), int(Q0.shape[1]), degree,
+                                  int(Q0.shape[0]), float(dt), _ptr(star), _ptr(E), _ptr(Q0)))
 
 
 def reference_matrices(degree: int):

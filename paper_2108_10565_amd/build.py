@@ -3,8 +3,10 @@
 Steps: (1) compile and run the host table generator (``csrc/gen_tables.cpp``
 + ``csrc/basis.cpp``), which writes ``csrc/generated/khat_tables.h``;
 (2) compile every ``.hip`` / ``.cpp`` source with hipcc for gfx950, one
-object per source (per degree for the fused kernel, in parallel);
-(3) link ``paper_2108_10565_amd/libstp.so``.
+object per source (per quantity count and degree for the fused kernels, in
+parallel);
+(3) link ``paper_2108_10565_amd/libstp.so``.  The tile shape of each
+degree's fused kernels comes from ``tiles.json`` (written by ``autotune.py``).
 """
 from __future__ import annotations
 
@@ -54,16 +56,43 @@ def generate_tables():
         os.replace(tmp, out)
 
 
+TILES = os.path.join(PKG, "tiles.json")
+
+
+def tile_table(path: str = TILES) -> dict:
+    """{degree: (threads, chunk)} of the fused kernels, as the autotuner wrote it."""
+    import json
+    t = json.load(open(path))["tiles"]
+    return {int(n): (int(v[0]), int(v[1])) for n, v in t.items()}
+
+
+# quantity counts with compiled kernels: poroelastic, damped Maxwell
+QUANTITY_COUNTS = (13, 6)
+
+
+def fused_object_name(nq: int, n: int) -> str:
+    return f"kernel_fused_q{nq}_n{n}.o"
+
+
+def fused_object_cmd(n: int, threads: int, chunk: int, obj: str, nq: int = 13):
+    """hipcc command compiling the fused kernels of degree n for nq quantities
+    with one tile shape."""
+    return [HIPCC] + HIP_FLAGS + ["-x", "hip", f"-DSTP_NQ={nq}", f"-DSTP_DEGREE={n}",
+                                  f"-DSTP_TILE_THREADS={threads}", f"-DSTP_TILE_CHUNK={chunk}", "-c",
+                                  os.path.join(CSRC, "kernel_fused.hip"), "-o", obj]
+
+
 def _objects():
     jobs = []
     for src in ("stp_api.hip", "kernel_ref.hip", "peaks.hip", "basis.cpp"):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         extra = ["-x", "hip"] if src.endswith(".hip") else []
         jobs.append(([HIPCC] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
-    for n in DEGREES:
-        obj = os.path.join(BUILD, f"kernel_fused_n{n}.o")
-        jobs.append(([HIPCC] + HIP_FLAGS + ["-x", "hip", f"-DSTP_DEGREE={n}", "-c",
-                      os.path.join(CSRC, "kernel_fused.hip"), "-o", obj], obj))
+    tiles = tile_table()
+    for nq in QUANTITY_COUNTS:
+        for n in DEGREES:
+            obj = os.path.join(BUILD, fused_object_name(nq, n))
+            jobs.append((fused_object_cmd(n, *tiles[n], obj, nq), obj))
     return jobs
 
 

@@ -15,7 +15,12 @@
 
 namespace stp {
 
-constexpr int kNQ = 13;
+// Quantity counts the fused kernels are compiled for: the poroelastic system
+// and the damped Maxwell system of section "Other applications" (any system
+// whose source matrix is upper triangular runs through the same kernels).
+constexpr int kNQPoro = 13;
+constexpr int kNQMaxwell = 6;
+__host__ __device__ constexpr bool supported_nq(int nq) { return nq == kNQPoro || nq == kNQMaxwell; }
 constexpr int kMaxDegree = 7;
 
 __host__ __device__ constexpr int n_modes(int N) { return (N + 1) * (N + 2) * (N + 3) / 6; }
@@ -40,43 +45,56 @@ struct PredictArgs {
 
 // Bytes of workspace the mixed-precision path needs: the float residual of
 // every element between the residual and the correction kernels.
-inline size_t workspace_bytes(int N, int64_t n, int precision, int refine_steps) {
+inline size_t workspace_bytes(int nq, int N, int64_t n, int precision, int refine_steps) {
   if (precision == 0 || refine_steps == 0 || n <= 0) return 0;
-  const size_t raw = static_cast<size_t>(n) * kNQ * n_modes(N) * (N + 1) * sizeof(float);
+  const size_t raw = static_cast<size_t>(n) * nq * n_modes(N) * (N + 1) * sizeof(float);
   return (raw + 255) / 256 * 256;
 }
 
 // Launchers (one per kernel family); return hipSuccess or the launch error.
 hipError_t launch_reference_kernel(int N, const PredictArgs& a, hipStream_t stream);
-// The fused kernel is compiled once per degree (STP_DEGREE); each object
-// defines the specialisation for its degree.
-// valu_float_chain: run the float32 chain's green update on the vector ALU
-// instead of the matrix cores (kept for comparison measurements).
-template <int N>
-hipError_t launch_fused_degree(const PredictArgs& a, int precision, int refine_steps, float* workspace,
-                               bool valu_float_chain, hipStream_t stream);
-template <> hipError_t launch_fused_degree<0>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<1>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<2>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<3>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<4>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<5>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<6>(const PredictArgs&, int, int, float*, bool, hipStream_t);
-template <> hipError_t launch_fused_degree<7>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+// The fused kernels are compiled once per (quantity count STP_NQ, degree
+// STP_DEGREE); each object defines the specialisation for its pair.
+// valu_float_chain: the float32 chain's green update as sparse fused
+// multiply-adds on the vector ALU (default); false: on the matrix cores.
+template <int NQ, int N>
+hipError_t launch_fused(const PredictArgs& a, int precision, int refine_steps, float* workspace,
+                        bool valu_float_chain, hipStream_t stream);
+#define STP_DECLARE_FUSED(Q)                                                                             \
+  template <> hipError_t launch_fused<Q, 0>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 1>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 2>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 3>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 4>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 5>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 6>(const PredictArgs&, int, int, float*, bool, hipStream_t);  \
+  template <> hipError_t launch_fused<Q, 7>(const PredictArgs&, int, int, float*, bool, hipStream_t);
+STP_DECLARE_FUSED(13)
+STP_DECLARE_FUSED(6)
+#undef STP_DECLARE_FUSED
 
-inline hipError_t launch_fused_kernel(int N, const PredictArgs& a, int precision, int refine_steps,
-                                      float* workspace, bool valu_float_chain, hipStream_t stream) {
+template <int NQ>
+inline hipError_t launch_fused_nq(int N, const PredictArgs& a, int precision, int refine_steps, float* workspace,
+                                  bool valu_float_chain, hipStream_t stream) {
   switch (N) {
-    case 0: return launch_fused_degree<0>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 1: return launch_fused_degree<1>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 2: return launch_fused_degree<2>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 3: return launch_fused_degree<3>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 4: return launch_fused_degree<4>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 5: return launch_fused_degree<5>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 6: return launch_fused_degree<6>(a, precision, refine_steps, workspace, valu_float_chain, stream);
-    case 7: return launch_fused_degree<7>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 0: return launch_fused<NQ, 0>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 1: return launch_fused<NQ, 1>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 2: return launch_fused<NQ, 2>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 3: return launch_fused<NQ, 3>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 4: return launch_fused<NQ, 4>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 5: return launch_fused<NQ, 5>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 6: return launch_fused<NQ, 6>(a, precision, refine_steps, workspace, valu_float_chain, stream);
+    case 7: return launch_fused<NQ, 7>(a, precision, refine_steps, workspace, valu_float_chain, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+inline hipError_t launch_fused_kernel(int nq, int N, const PredictArgs& a, int precision, int refine_steps,
+                                      float* workspace, bool valu_float_chain, hipStream_t stream) {
+  if (nq == kNQPoro) return launch_fused_nq<kNQPoro>(N, a, precision, refine_steps, workspace, valu_float_chain, stream);
+  if (nq == kNQMaxwell)
+    return launch_fused_nq<kNQMaxwell>(N, a, precision, refine_steps, workspace, valu_float_chain, stream);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace stp

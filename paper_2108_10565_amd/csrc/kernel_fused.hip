@@ -3,7 +3,7 @@
 // N = STP_DEGREE.
 //
 // Mapping.  One lane per column (element e, quantity p, time mode u) of the
-// element's right-hand side b_pmu (eq:b_pmu); 13 (N+1) lanes per element,
+// element's right-hand side b_pmu (eq:b_pmu); kNQ (N+1) lanes per element,
 // kElems elements per workgroup (512 lanes at most), lanes ordered
 // quantity-major.
 // Every lane keeps b[m] for all modes m below the top degree block in
@@ -52,14 +52,25 @@
 namespace stp {
 namespace {
 
-// Tile shape per degree: threads per workgroup (upper bound; rounded to
+// Quantities of the system this object is compiled for: 13 (poroelastic) or
+// 6 (damped Maxwell, section "Other applications").
+#ifndef STP_NQ
+#error "compile once per quantity count with -DSTP_NQ=Q"
+#endif
+constexpr int kNQ = STP_NQ;
+static_assert(supported_nq(kNQ), "quantity count without kernels");
+
+// Tile shape of this degree: threads per workgroup (upper bound; rounded to
 // whole elements and waves) and modes per chunk (degree blocks are split
-// evenly).  Chosen by a sweep on MI355X at 262,144 elements over {512, 256}
-// threads x {10, 6} modes; 512 x 10 was best or within 3% at N = 4..6, and
-// 256 threads gave 2.5% at N = 3.
-constexpr int kTileThreads[kMaxDegree + 1] = {512, 512, 512, 256, 512, 512, 512, 512};
+// evenly).  Both come from the build, which takes them from the table the
+// autotuner writes after timing every candidate shape on the device.
+#if !defined(STP_TILE_THREADS) || !defined(STP_TILE_CHUNK)
+#error "compile with -DSTP_TILE_THREADS=T -DSTP_TILE_CHUNK=C (the tile table of the build)"
+#endif
+constexpr int kTileThreadsN = STP_TILE_THREADS;
+constexpr int kChunkMax = STP_TILE_CHUNK;
+static_assert(kTileThreadsN >= 64 && kTileThreadsN <= 1024 && kChunkMax >= 1, "tile shape");
 constexpr int kMaxElems = 16;
-constexpr int kChunkMax = 10;
 // Non-zero columns kept per lane of a star-matrix row (union over the three
 // directions).  The poroelastic Jacobians need at most 6 (normal-stress and
 // pressure rows couple to the 6 velocities; velocity rows to 3 stresses and
@@ -90,7 +101,8 @@ struct Cfg {
   static constexpr int DN = block_size(N);         // modes of the top block (largest block)
   static constexpr int kCols = kNQ * T;            // lanes per element
   static constexpr int kElems =                    // elements per workgroup
-      (kTileThreads[N] / kCols) < kMaxElems ? (kTileThreads[N] / kCols) : kMaxElems;
+      (kTileThreadsN / kCols) < kMaxElems ? (kTileThreadsN / kCols) : kMaxElems;
+  static_assert(kElems >= 1, "the tile must hold at least one element");
   static constexpr int kThreads = (kElems * kCols + 63) / 64 * 64;
   static constexpr int kSlots = kElems + 1;        // + one dummy slot for spare lanes
   static constexpr int kChunk = kChunkMax < DN ? kChunkMax : DN;
@@ -311,7 +323,7 @@ __device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y
 }
 
 // Copies columns [m0 T, m0 T + PER) of the (element, quantity) rows of the
-// group (a [n][13][B T] array in memory) into the chunk buffer `buf` (block
+// group (a [n][kNQ][B T] array in memory) into the chunk buffer `buf` (block
 // layout of Cfg::blk), converted to R.  Every lane issues all its loads
 // before its LDS stores, so the group waits for one memory latency, not one
 // per row segment.
@@ -1088,24 +1100,8 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void mfma_solve_kernel(PredictArg
           constexpr int mg0 = decltype(grc)::value * kMG;
           constexpr int gm = (c - mg0) < kMG ? (c - mg0) : kMG;
           constexpr int nkb = (3 * gm + 3) / 4;
-          __builtin_amdgcn_sched_barrier(0);
-          // star products of the group's modes -> Y rows k = 3 mm + j of this wave
-          static_for<0, gm>([&](auto mmc) __attribute__((always_inline)) {
-            constexpr int mm = decltype(mmc)::value;
-            R y0, y1, y2;
-            L.template star<mg0 + mm>(bufX, a, e0, es, p, u, active, y0, y1, y2);
-            yb[(3 * mm + 0) * kYStride + lane] = y0;
-            yb[(3 * mm + 1) * kYStride + lane] = y1;
-            yb[(3 * mm + 2) * kYStride + lane] = y2;
-          });
-          // operands: B = Y (k = 4 kb + l / 16, column l % 16 of tile ct);
-          // A = -Khat rows 16 rt + l % 16 of (mode, direction) k = 4 kb + l / 16
-          float bv[4][nkb];
-          static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
-            constexpr int ct = decltype(ctc)::value;
-#pragma unroll
-            for (int kb = 0; kb < nkb; ++kb) bv[ct][kb] = yb[(4 * kb + lrow) * kYStride + 16 * ct + lcol];
-          });
+          // A = -Khat rows 16 rt + l % 16 of (mode, direction) k = 4 kb + l / 16,
+          // loaded first so that the loads overlap the star products
           constexpr int base = stp_gen::KhatMfma<N>::off[m0 + mg0];
           float av[RG][nkb];
 #pragma unroll
@@ -1122,17 +1118,36 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void mfma_solve_kernel(PredictArg
               av[rt][kb] = live ? v : 0.0f;
             }
           }
+          // star products of the group's modes -> Y rows k = 3 mm + j of this wave
+          static_for<0, gm>([&](auto mmc) __attribute__((always_inline)) {
+            constexpr int mm = decltype(mmc)::value;
+            R y0, y1, y2;
+            L.template star<mg0 + mm>(bufX, a, e0, es, p, u, active, y0, y1, y2);
+            yb[(3 * mm + 0) * kYStride + lane] = y0;
+            yb[(3 * mm + 1) * kYStride + lane] = y1;
+            yb[(3 * mm + 2) * kYStride + lane] = y2;
+          });
+          // B = Y (k = 4 kb + l / 16, column l % 16 of tile ct)
+          float bv[4][nkb];
           static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
             constexpr int ct = decltype(ctc)::value;
-            if (ct < nct) {
-              static_for<0, RG>([&](auto rtc) __attribute__((always_inline)) {
-                constexpr int rt = decltype(rtc)::value;
 #pragma unroll
-                for (int kb = 0; kb < nkb; ++kb)
-                  acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt][kb], bv[ct][kb], acc[ct][rt], 0, 0, 0);
-              });
-            }
+            for (int kb = 0; kb < nkb; ++kb) bv[ct][kb] = yb[(4 * kb + lrow) * kYStride + 16 * ct + lcol];
           });
+          // k-blocks outermost: consecutive instructions update different
+          // accumulator tiles, so none waits on the previous one's result
+#pragma unroll
+          for (int kb = 0; kb < nkb; ++kb) {
+            static_for<0, 4>([&](auto ctc) __attribute__((always_inline)) {
+              constexpr int ct = decltype(ctc)::value;
+              if (ct < nct) {
+                static_for<0, RG>([&](auto rtc) __attribute__((always_inline)) {
+                  constexpr int rt = decltype(rtc)::value;
+                  acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt][kb], bv[ct][kb], acc[ct][rt], 0, 0, 0);
+                });
+              }
+            });
+          }
         });
       }
     });
@@ -1270,8 +1285,8 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
 }  // namespace
 
 template <>
-hipError_t launch_fused_degree<STP_DEGREE>(const PredictArgs& a, int precision, int refine_steps,
-                                           float* workspace, bool valu_float_chain, hipStream_t stream) {
+hipError_t launch_fused<STP_NQ, STP_DEGREE>(const PredictArgs& a, int precision, int refine_steps,
+                                            float* workspace, bool valu_float_chain, hipStream_t stream) {
   constexpr int N = STP_DEGREE;
   using C = Cfg<N>;
   const int64_t groups = (a.n + C::kElems - 1) / C::kElems;

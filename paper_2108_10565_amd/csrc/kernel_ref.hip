@@ -23,6 +23,8 @@
 namespace stp {
 namespace {
 
+constexpr int kNQ = kNQPoro;  // the reference kernel is for the poroelastic system
+
 template <int N>
 __device__ __forceinline__ const double* khat_dense();
 #define STP_KHAT_DENSE(NN) \

@@ -36,23 +36,24 @@ constexpr int kFlagNonFinite = 1;
 constexpr int kFlagNotUpper = 2;
 constexpr int kFlagSingular = 4;
 
-__global__ void validate_kernel(int64_t n, int B, double dt, const double* star, const double* E,
+__global__ void validate_kernel(int64_t n, int nq, int B, double dt, const double* star, const double* E,
                                 const double* Q0, int* flags) {
-  const int64_t per = 3 * 169 + 169 + 13 * static_cast<int64_t>(B);
+  const int64_t q2 = static_cast<int64_t>(nq) * nq;
+  const int64_t per = 4 * q2 + nq * static_cast<int64_t>(B);
   int f = 0;
   for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < n * per;
        t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t e = t / per, r = t % per;
     double v;
-    if (r < 3 * 169) {
-      v = star[e * 3 * 169 + r];
-    } else if (r < 4 * 169) {
-      const int k = static_cast<int>(r - 3 * 169), row = k / 13, col = k % 13;
-      v = E[e * 169 + k];
+    if (r < 3 * q2) {
+      v = star[e * 3 * q2 + r];
+    } else if (r < 4 * q2) {
+      const int k = static_cast<int>(r - 3 * q2), row = k / nq, col = k % nq;
+      v = E[e * q2 + k];
       if (row > col && v != 0.0) f |= kFlagNotUpper;
       if (row == col && dt * v >= 0.5) f |= kFlagSingular;
     } else {
-      v = Q0[e * 13 * B + (r - 4 * 169)];
+      v = Q0[e * nq * B + (r - 4 * q2)];
     }
     if (!std::isfinite(v)) f |= kFlagNonFinite;
   }
@@ -72,18 +73,22 @@ stp_status check_common(stp_handle h, int degree, int64_t n, double dt) {
 stp_status check_predict(stp_handle h, int degree, int64_t n, double dt, const double* star, const double* E,
                          const double* Q0, double* Q, stp_precision precision, int refine_steps,
                          const void* workspace, size_t workspace_bytes, unsigned flags,
-                         bool workspace_checked = true) {
+                         bool workspace_checked = true, int nq = STP_NQ) {
+  if (!stp::supported_nq(nq))
+    return fail(h, STP_EINVAL, "no kernels for " + std::to_string(nq) + " quantities (13 or 6)");
   stp_status st = check_common(h, degree, n, dt);
   if (st != STP_OK) return st;
   if (precision != STP_FP64 && precision != STP_FP32_REFINE) return fail(h, STP_EINVAL, "unknown precision");
   if (refine_steps < 0 || refine_steps > STP_MAX_REFINE)
     return fail(h, STP_EINVAL, "refine_steps must be in 0..3");
-  if (flags & ~(STP_FLAG_REFERENCE_KERNEL | STP_FLAG_VALU_FLOAT_CHAIN)) return fail(h, STP_EINVAL, "unknown flags");
+  if (flags & ~(STP_FLAG_REFERENCE_KERNEL | STP_FLAG_MFMA_FLOAT_CHAIN)) return fail(h, STP_EINVAL, "unknown flags");
   if ((flags & STP_FLAG_REFERENCE_KERNEL) && precision != STP_FP64)
     return fail(h, STP_EINVAL, "the reference kernel is float64 only");
   if (n == 0) return STP_OK;
   if (!star || !E || !Q0 || !Q) return fail(h, STP_EINVAL, "NULL array pointer");
-  const size_t need = stp::workspace_bytes(degree, n, static_cast<int>(precision), refine_steps);
+  if ((flags & STP_FLAG_REFERENCE_KERNEL) && nq != STP_NQ)
+    return fail(h, STP_EINVAL, "the reference kernel is for the 13-quantity system only");
+  const size_t need = stp::workspace_bytes(nq, degree, n, static_cast<int>(precision), refine_steps);
   if (workspace_checked && need > 0 && (!workspace || workspace_bytes < need))
     return fail(h, STP_EWORKSPACE,
                 "workspace of " + std::to_string(need) + " bytes needed, got " + std::to_string(workspace_bytes));
@@ -93,15 +98,15 @@ stp_status check_predict(stp_handle h, int degree, int64_t n, double dt, const d
 // Launches one checked prediction request on `stream`.
 stp_status launch_predict(stp_handle h, hipStream_t stream, int degree, int64_t n, double dt, const double* star,
                           const double* E, const double* Q0, double* Q, double* Qint, stp_precision precision,
-                          int refine_steps, void* workspace, unsigned flags) {
+                          int refine_steps, void* workspace, unsigned flags, int nq = STP_NQ) {
   if (n == 0) return STP_OK;
   stp::PredictArgs a{n, dt, star, E, Q0, Q, Qint};
   hipError_t err;
   if (flags & STP_FLAG_REFERENCE_KERNEL)
     err = stp::launch_reference_kernel(degree, a, stream);
   else
-    err = stp::launch_fused_kernel(degree, a, static_cast<int>(precision), refine_steps,
-                                   static_cast<float*>(workspace), (flags & STP_FLAG_VALU_FLOAT_CHAIN) != 0,
+    err = stp::launch_fused_kernel(nq, degree, a, static_cast<int>(precision), refine_steps,
+                                   static_cast<float*>(workspace), (flags & STP_FLAG_MFMA_FLOAT_CHAIN) == 0,
                                    stream);
   if (err != hipSuccess) return hip_fail(h, err, "kernel launch");
   return STP_OK;
@@ -169,6 +174,18 @@ stp_status scratch_address(stp_handle h, hipStream_t stream, void** out) {
   return STP_OK;
 }
 
+// Parallel branches of a staged graph: the batches of one stage go round
+// robin to this many streams.
+constexpr int kBranches = 4;
+
+stp_status check_stages(stp_handle h, int n_stages, const int* stage_sizes) {
+  if (n_stages < 0) return fail(h, STP_EINVAL, "n_stages < 0");
+  if (n_stages > 0 && !stage_sizes) return fail(h, STP_EINVAL, "NULL stage_sizes");
+  for (int s = 0; s < n_stages; ++s)
+    if (stage_sizes[s] < 0) return fail(h, STP_EINVAL, "stage " + std::to_string(s) + " has a negative size");
+  return STP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -183,7 +200,7 @@ stp_status stp_predict_static(stp_handle handle, void* hip_stream, int degree, i
   const stp_status st = check_predict(handle, degree, n_elements, dt, star, E, Q0, Q, precision, refine_steps,
                                       nullptr, 0, flags, /*workspace_checked=*/false);
   if (st != STP_OK) return st;
-  const size_t need = stp::workspace_bytes(degree, n_elements, static_cast<int>(precision), refine_steps);
+  const size_t need = stp::workspace_bytes(STP_NQ, degree, n_elements, static_cast<int>(precision), refine_steps);
   if (need > kScratchBytes)
     return fail(handle, STP_EWORKSPACE,
                 "stp_predict_static: " + std::to_string(need) + " bytes of scratch needed, at most " +
@@ -216,8 +233,31 @@ stp_status stp_workspace_size(stp_handle handle, int degree, int64_t n_elements,
   if (n_elements < 0) return fail(handle, STP_EINVAL, "n_elements < 0");
   if (precision != STP_FP64 && precision != STP_FP32_REFINE) return fail(handle, STP_EINVAL, "precision");
   if (refine_steps < 0 || refine_steps > STP_MAX_REFINE) return fail(handle, STP_EINVAL, "refine_steps");
-  *bytes = stp::workspace_bytes(degree, n_elements, static_cast<int>(precision), refine_steps);
+  *bytes = stp::workspace_bytes(STP_NQ, degree, n_elements, static_cast<int>(precision), refine_steps);
   return STP_OK;
+}
+
+stp_status stp_workspace_size_nq(stp_handle handle, int n_quantities, int degree, int64_t n_elements,
+                                 stp_precision precision, int refine_steps, size_t* bytes) {
+  if (!handle || !bytes) return STP_EINVAL;
+  if (!stp::supported_nq(n_quantities)) return fail(handle, STP_EINVAL, "unsupported quantity count");
+  const stp_status st = stp_workspace_size(handle, degree, n_elements, precision, refine_steps, bytes);
+  if (st != STP_OK) return st;
+  *bytes = stp::workspace_bytes(n_quantities, degree, n_elements, static_cast<int>(precision), refine_steps);
+  return STP_OK;
+}
+
+stp_status stp_predict_nq(stp_handle handle, void* hip_stream, int n_quantities, int degree, int64_t n_elements,
+                          double dt, const double* star, const double* E, const double* Q0, double* Q,
+                          double* Qint, stp_precision precision, int refine_steps, void* workspace,
+                          size_t workspace_bytes, unsigned flags) {
+  if (!handle) return STP_EINVAL;
+  handle->last_error.clear();
+  const stp_status st = check_predict(handle, degree, n_elements, dt, star, E, Q0, Q, precision, refine_steps,
+                                      workspace, workspace_bytes, flags, true, n_quantities);
+  if (st != STP_OK) return st;
+  return launch_predict(handle, static_cast<hipStream_t>(hip_stream), degree, n_elements, dt, star, E, Q0, Q, Qint,
+                        precision, refine_steps, workspace, flags, n_quantities);
 }
 
 stp_status stp_predict(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
@@ -299,6 +339,116 @@ stp_status stp_graph_create(stp_handle handle, void* hip_stream, int n_batches, 
   return STP_OK;
 }
 
+stp_status stp_staged_workspace_size(stp_handle handle, int n_stages, const int* stage_sizes,
+                                     const stp_batch* batches, stp_precision precision, int refine_steps,
+                                     size_t* bytes) {
+  if (!handle || !bytes) return STP_EINVAL;
+  const stp_status st = check_stages(handle, n_stages, stage_sizes);
+  if (st != STP_OK) return st;
+  size_t need = 0;
+  int b0 = 0;
+  for (int s = 0; s < n_stages; ++s) {
+    size_t stage = 0;
+    for (int i = b0; i < b0 + stage_sizes[s]; ++i) {
+      size_t b = 0;
+      const stp_status bs = stp_workspace_size(handle, batches[i].degree, batches[i].n_elements, precision,
+                                               refine_steps, &b);
+      if (bs != STP_OK) return fail(handle, bs, "batch " + std::to_string(i) + ": " + handle->last_error);
+      stage += (b + 255) / 256 * 256;
+    }
+    need = stage > need ? stage : need;
+    b0 += stage_sizes[s];
+  }
+  *bytes = need;
+  return STP_OK;
+}
+
+stp_status stp_graph_create_staged(stp_handle handle, void* hip_stream, int n_stages, const int* stage_sizes,
+                                   const stp_batch* batches, stp_precision precision, int refine_steps,
+                                   void* workspace, size_t workspace_bytes, unsigned flags, stp_graph* graph) {
+  if (!handle || !graph) return STP_EINVAL;
+  *graph = nullptr;
+  handle->last_error.clear();
+  if (!hip_stream) return fail(handle, STP_EINVAL, "graph capture needs a non-NULL stream");
+  stp_status st = check_stages(handle, n_stages, stage_sizes);
+  if (st != STP_OK) return st;
+  int n_batches = 0;
+  for (int s = 0; s < n_stages; ++s) n_batches += stage_sizes[s];
+  // every batch is checked against the whole workspace here; the per-stage
+  // split is checked below
+  st = check_batches(handle, n_batches, batches, precision, refine_steps, workspace, workspace_bytes, flags);
+  if (st != STP_OK) return st;
+  size_t need = 0;
+  st = stp_staged_workspace_size(handle, n_stages, stage_sizes, batches, precision, refine_steps, &need);
+  if (st != STP_OK) return st;
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(handle, STP_EWORKSPACE, "staged workspace of " + std::to_string(need) + " bytes needed");
+  stp_graph g = new (std::nothrow) stp_graph_s();
+  if (!g) return fail(handle, STP_ENOMEM, "out of host memory");
+  hipStream_t s0 = static_cast<hipStream_t>(hip_stream);
+  // branch streams (default priority) and fork / join events, used only
+  // while capturing
+  hipStream_t br[kBranches] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {};
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < kBranches && err == hipSuccess; ++i) err = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
+  for (int i = 0; i < kBranches && err == hipSuccess; ++i) err = hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming);
+  bool capturing = false;
+  if (err == hipSuccess) {
+    err = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+    capturing = err == hipSuccess;
+  }
+  int b0 = 0;
+  for (int s = 0; s < n_stages && err == hipSuccess && st == STP_OK; ++s) {
+    const int nb = stage_sizes[s];
+    const int used = nb < kBranches ? nb : kBranches;
+    err = hipEventRecord(fork_ev, s0);
+    for (int k = 0; k < used && err == hipSuccess; ++k) err = hipStreamWaitEvent(br[k], fork_ev, 0);
+    size_t off = 0;
+    for (int i = 0; i < nb && err == hipSuccess && st == STP_OK; ++i) {
+      const stp_batch& b = batches[b0 + i];
+      size_t wb = 0;
+      (void)stp_workspace_size(handle, b.degree, b.n_elements, precision, refine_steps, &wb);
+      void* ws = wb ? static_cast<void*>(static_cast<char*>(workspace) + off) : nullptr;
+      off += (wb + 255) / 256 * 256;
+      st = launch_predict(handle, br[i % kBranches], b.degree, b.n_elements, b.dt, b.star, b.E, b.Q0, b.Q, b.Qint,
+                          precision, refine_steps, ws, flags);
+      if (st != STP_OK) handle->last_error = "batch " + std::to_string(b0 + i) + ": " + handle->last_error;
+    }
+    for (int k = 0; k < used && err == hipSuccess; ++k) {
+      err = hipEventRecord(join_ev[k], br[k]);
+      if (err == hipSuccess) err = hipStreamWaitEvent(s0, join_ev[k], 0);
+    }
+    b0 += nb;
+  }
+  const std::string launch_error = handle->last_error;
+  if (capturing) {
+    const hipError_t e2 = hipStreamEndCapture(s0, &g->graph);
+    if (err == hipSuccess) err = e2;
+  }
+  if (st == STP_OK && err != hipSuccess) st = hip_fail(handle, err, "staged graph capture");
+  if (st == STP_OK) {
+    err = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) st = hip_fail(handle, err, "hipGraphInstantiate");
+  } else if (!launch_error.empty()) {
+    handle->last_error = launch_error;
+  }
+  for (int i = 0; i < kBranches; ++i) {
+    if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+    if (br[i]) (void)hipStreamDestroy(br[i]);
+  }
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
+  if (st != STP_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *graph = g;
+  return STP_OK;
+}
+
 stp_status stp_graph_launch(stp_graph graph, void* hip_stream) {
   if (!graph || !graph->exec) return STP_EINVAL;
   return hipGraphLaunch(graph->exec, static_cast<hipStream_t>(hip_stream)) == hipSuccess ? STP_OK : STP_EHIP;
@@ -312,9 +462,11 @@ stp_status stp_graph_destroy(stp_graph graph) {
   return (e1 == hipSuccess && e2 == hipSuccess) ? STP_OK : STP_EHIP;
 }
 
-stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
-                        const double* star, const double* E, const double* Q0) {
+stp_status stp_validate_nq(stp_handle handle, void* hip_stream, int n_quantities, int degree, int64_t n_elements,
+                           double dt, const double* star, const double* E, const double* Q0) {
   stp_status st = check_common(handle, degree, n_elements, dt);
+  if (st == STP_OK && !stp::supported_nq(n_quantities))
+    st = fail(handle, STP_EINVAL, "unsupported quantity count");
   if (st != STP_OK) return st;
   handle->last_error.clear();
   if (n_elements == 0) return STP_OK;
@@ -327,7 +479,8 @@ stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t
   err = hipMemcpyAsync(dflags, &hflags, sizeof(int), hipMemcpyHostToDevice, stream);
   if (err == hipSuccess) {
     const int B = stp::n_modes(degree);
-    hipLaunchKernelGGL(validate_kernel, dim3(1024), dim3(256), 0, stream, n_elements, B, dt, star, E, Q0,
+    hipLaunchKernelGGL(validate_kernel, dim3(1024), dim3(256), 0, stream, n_elements, n_quantities, B, dt, star,
+                       E, Q0,
                        dflags);
     err = hipGetLastError();
   }
@@ -340,6 +493,11 @@ stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t
   if (hflags & kFlagNotUpper) return fail(handle, STP_ENOTUPPER, "E has a non-zero below its diagonal");
   if (hflags & kFlagSingular) return fail(handle, STP_ESINGULAR, "dt * E_pp >= 0.5 for some quantity");
   return STP_OK;
+}
+
+stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
+                        const double* star, const double* E, const double* Q0) {
+  return stp_validate_nq(handle, hip_stream, STP_NQ, degree, n_elements, dt, star, E, Q0);
 }
 
 stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z, double* Sinv_w, double* Khat) {

@@ -357,6 +357,102 @@ def lts_cycle(batches):
             if s % rate ** b.meta["cluster"] == 0]
 
 
+def lts_stages(batches):
+    """The cycle of ``lts_cycle`` split by sub-step: a list of lists of batch
+    indices; the batches of one sub-step are independent of each other."""
+    if not batches:
+        return []
+    rate = batches[0].meta["rate"]
+    K = 1 + max(b.meta["cluster"] for b in batches)
+    return [[i for i, b in enumerate(batches) if s % rate ** b.meta["cluster"] == 0]
+            for s in range(rate ** (K - 1))]
+
+
+# ----------------------------------------------------------------------------
+# a second system with a stiff source: damped Maxwell equations
+# ----------------------------------------------------------------------------
+#
+# Section "Other applications": eps E_t = curl H - sigma E + j and
+# mu H_t = -curl E (Faraday's law; the sign printed there in front of curl E
+# is read as a typo, since with it the Jacobians have imaginary eigenvalues
+# and the system is not hyperbolic).  Quantities (Ex, Ey, Ez, Hx, Hy, Hz);
+# with curl expanded, q_t + A q_x + B q_y + C q_z = Es q with the diagonal
+# (hence upper triangular) source Es = diag(-sigma/eps x 3, 0 x 3); the
+# current density j is an external source and not part of the predictor.
+# Non-dimensional units: edge length ~1, relative eps and mu.
+
+MAXWELL_QUANTITIES = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+EX, EY, EZ, HX, HY, HZ = range(6)
+
+
+def maxwell_jacobians(eps, mu, sigma):
+    """A, B, C, Es of the damped Maxwell system, shape (n, 6, 6)."""
+    eps, mu, sigma = (np.atleast_1d(np.asarray(v, float)) for v in (eps, mu, sigma))
+    n = np.broadcast(eps, mu, sigma).size
+    eps, mu, sigma = (np.broadcast_to(v, (n,)) for v in (eps, mu, sigma))
+    J = np.zeros((3, n, 6, 6))
+    # E_t - (1/eps) curl H = -(sigma/eps) E, curl H = (dy Hz - dz Hy, dz Hx - dx Hz, dx Hy - dy Hx)
+    # H_t + (1/mu) curl E = 0,             curl E = (dy Ez - dz Ey, dz Ex - dx Ez, dx Ey - dy Ex)
+    for k in range(3):                       # direction x_k
+        i1, i2 = (k + 1) % 3, (k + 2) % 3    # cyclic pair: curl_i1 has +d_k of component i2
+        J[k][:, EX + i1, HX + i2] = 1.0 / eps
+        J[k][:, EX + i2, HX + i1] = -1.0 / eps
+        J[k][:, HX + i1, EX + i2] = -1.0 / mu
+        J[k][:, HX + i2, EX + i1] = 1.0 / mu
+    Es = np.zeros((n, 6, 6))
+    for i in range(3):
+        Es[:, EX + i, EX + i] = -sigma / eps
+    return J[0], J[1], J[2], Es
+
+
+def make_maxwell(N, n, seed=0, name=None, zmin=-2.0, zmax=6.0):
+    """Seeded damped-Maxwell workload: tetrahedra of edge ~1 (regular,
+    rotated, vertices jittered by U[-0.1, 0.1]^3, edges in [0.8, 1.2]),
+    eps ~ U[1, 10], mu ~ U[1, 2], and sigma chosen per element so that the
+    stiffness dt sigma / eps is log-uniform in [10^zmin, 10^zmax]; global
+    time step from the CFL condition with the light speed 1/sqrt(eps mu).
+    Q0 ~ N(0, 1).  Returns a Workload with six quantities."""
+    nchunks = (n + CHUNK - 1) // CHUNK
+    parts, cfl_min = [], np.inf
+    for c in range(nchunks):
+        count = min(CHUNK, n - c * CHUNK)
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, c, 77])))
+        eps = rng.uniform(1.0, 10.0, count)
+        mu = rng.uniform(1.0, 2.0, count)
+        v = random_tets(rng, count, edge=1.0, jitter=0.1, lo=0.8, hi=1.2)
+        cfl = insphere_diameter(v) * np.sqrt(eps * mu)
+        z = 10.0 ** rng.uniform(zmin, zmax, count)
+        Q0 = rng.standard_normal((count, 6, n_modes(N)))
+        parts.append(dict(eps=eps, mu=mu, v=v, z=z, Q0=Q0))
+        cfl_min = min(cfl_min, float(cfl.min()))
+    dt = 0.5 / (2 * N + 1) * cfl_min
+    stars, Es, Q0s, mats = [], [], [], {"eps": [], "mu": [], "sigma": []}
+    for p in parts:
+        sigma = p["z"] * p["eps"] / dt
+        A, B, C, Esrc = maxwell_jacobians(p["eps"], p["mu"], sigma)
+        stars.append(star_matrices(A, B, C, p["v"]))
+        Es.append(Esrc)
+        Q0s.append(p["Q0"])
+        for k, val in (("eps", p["eps"]), ("mu", p["mu"]), ("sigma", sigma)):
+            mats[k].append(val)
+    mats = {k: np.concatenate(v) for k, v in mats.items()}
+    return Workload(name=name or f"maxwell_N{N}_n{n}_s{seed}", N=N, n=n, dt=dt,
+                    star=np.ascontiguousarray(np.concatenate(stars)), E=np.ascontiguousarray(np.concatenate(Es)),
+                    Q0=np.ascontiguousarray(np.concatenate(Q0s)),
+                    meta=dict(seed=seed, kind="maxwell", n_total=n, materials=mats, quantities=MAXWELL_QUANTITIES))
+
+
+MAXWELL_CONFIGS = {
+    # damped Maxwell, N=6, 262,144 elements, dt sigma / eps from 1e-2 to 1e6
+    "maxwell_n6_262144": dict(seed=6, N=6, n=262144),
+}
+
+
+def make_maxwell_workload(name):
+    cfg = MAXWELL_CONFIGS[name]
+    return make_maxwell(cfg["N"], cfg["n"], seed=cfg["seed"], name=name)
+
+
 def stiffness(w: "Workload") -> np.ndarray:
     """dt |E_uf,uf| of every element of a workload."""
     return w.dt * np.abs(w.E[:, UF, UF])

@@ -110,6 +110,45 @@ def test_graph_of_one_lts_cycle_replays(lts_small, precision, refine):
     g.close()
 
 
+@pytest.mark.parametrize("precision,refine", [("fp64", 0), ("fp32_refine", 1)])
+def test_staged_graph_parallel_branches_replays(lts_small, precision, refine):
+    """The cycle captured with the batches of each sub-step on parallel
+    branches (stp_graph_create_staged): every replay, with eager work in
+    between, equals the eager batched call bitwise; after Q0 is doubled in
+    place a replay gives exactly twice Q."""
+    _say(f"[gpu] staged graph LTS cycle precision={precision}")
+    stages = wl.lts_stages(lts_small)
+    base = _batches(lts_small)
+    eager = api.predict_batched([dict(b) for b in base], precision=precision, refine_steps=refine)
+    torch.cuda.synchronize()
+    order = [i for st in stages for i in st]
+    batches, seen = [], {}
+    for i in order:
+        if i not in seen:
+            b = dict(base[i])
+            b["Q"] = torch.full_like(eager[i]["Q"], float("nan"))
+            b["Qint"] = torch.full_like(eager[i]["Qint"], float("nan"))
+            seen[i] = b
+        batches.append(seen[i])
+    g = api.Graph(batches, precision=precision, refine_steps=refine, stages=[len(s) for s in stages])
+    scratch = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        for i, b in seen.items():
+            assert torch.equal(b["Q"], eager[i]["Q"]) and torch.equal(b["Qint"], eager[i]["Qint"]), (rep, i)
+        scratch.mul_(1.0001).add_(1.0)
+        torch.cuda.synchronize()
+        _say(f"  replay {rep}: {len(order)} launches in {len(stages)} stages equal the eager call")
+    for b in base:
+        b["Q0"].mul_(2.0)
+    g.launch()
+    torch.cuda.synchronize()
+    for i, b in seen.items():
+        assert torch.equal(b["Q"], 2.0 * eager[i]["Q"]), i
+    g.close()
+
+
 def test_measured_machine_ceilings_are_plausible():
     """stp_measure_peaks: positive, and below 1.2x the published MI355X
     figures (FP64 vector and matrix 78.6 TFLOP/s, HBM 8 TB/s), which catches

@@ -27,6 +27,7 @@ KERNELS = {
     "reference": dict(reference_kernel=True),
     "fused_fp64": dict(precision="fp64"),
     "fused_fp32_refine2": dict(precision="fp32_refine", refine_steps=2),
+    "mfma_fp32_refine2": dict(precision="fp32_refine", refine_steps=2, mfma_float_chain=True),
 }
 
 
@@ -90,7 +91,7 @@ def test_degrees_ragged(kernel, N, n):
     _check(Q, Qi, Xo, Io)
 
 
-@pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2"])
+@pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2", "mfma_fp32_refine2"])
 @pytest.mark.parametrize("N,n", [(3, 10), (4, 16), (6, 11)])
 def test_several_groups_with_ragged_tail(kernel, N, n):
     """Every element against the oracle where the fused kernel's workgroups
@@ -279,7 +280,7 @@ def test_general_operators_dense_star_coupling_chains(kernel, N, n):
     _check(Q.cpu().numpy(), Qi.cpu().numpy(), Xo, Io)
 
 
-@pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2"])
+@pytest.mark.parametrize("kernel", ["fused_fp64", "fused_fp32_refine2", "mfma_fp32_refine2"])
 def test_one_dense_star_row_in_a_group(kernel):
     """Poroelastic elements, one of which has a star row with more than six
     non-zero columns: its whole workgroup takes the dense-star path, the

@@ -29,14 +29,15 @@ BOUND = 1e-12          # two decades below the GPU gate of 1e-10
 def per_quantity_bound(N, star, E, Q0, dt):
     Y, r, D = stp.assemble(N, star, E, Q0, dt)
     X, _ = stp.solve_element(N, star, E, Q0, dt)
-    x = (X.reshape(13, -1) / D[:, None]).reshape(-1)     # equilibrated unknowns
+    nq = len(D)
+    x = (X.reshape(nq, -1) / D[:, None]).reshape(-1)     # equilibrated unknowns
     res = (r.astype(np.longdouble) - Y.astype(np.longdouble) @ x.astype(np.longdouble)).astype(np.float64)
     pert = np.abs(res) + 16 * EPS * (np.abs(Y) @ np.abs(x) + np.abs(r))
     dx = np.abs(np.linalg.inv(Y)) @ pert + EPS * np.abs(x)
     # quantity-wise scaling by D does not change a quantity's relative error
-    dq = np.linalg.norm(dx.reshape(13, -1), axis=1)
-    xq = np.linalg.norm(x.reshape(13, -1), axis=1)
-    return dq / xq, np.linalg.norm(X.reshape(13, -1), axis=1)
+    dq = np.linalg.norm(dx.reshape(nq, -1), axis=1)
+    xq = np.linalg.norm(x.reshape(nq, -1), axis=1)
+    return dq / xq, np.linalg.norm(X.reshape(nq, -1), axis=1)
 
 
 def _assert_bound(b, norms, label):
