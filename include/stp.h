@@ -183,6 +183,62 @@ stp_status stp_validate_nq(stp_handle handle, void* hip_stream, int n_quantities
                            int degree, int64_t n_elements, double dt,
                            const double* star, const double* E, const double* Q0);
 
+/* ---- Corrector: one ADER-DG step with the predictor ------------------------
+ *
+ * Section "ADER-DG discretisation": the semi-discrete system eq:semi_discrete
+ * (volume term after integration by parts, Godunov flux across the four
+ * faces, source term) integrated over one time step with the predictor's
+ * time-integrated DOFs Qint in place of the solution:
+ *
+ *   Q <- Q + sum_j A^j Qint V^j + E Qint
+ *          - sum_f ( Gp_f Qint Fl_f + Gm_f Qint_nb(f) Fn_{f, j(f), h(f)} )
+ *
+ * with A^j the star matrices and E the source (both NOT dt-scaled; Qint
+ * already integrates over the step).  Reference tables (divided by the mass
+ * M_kk of the test function k; face integrals over the face's parameter
+ * triangle {s, t >= 0, s + t <= 1}, faces of the reference tetrahedron with
+ * local vertex triples (0,2,1), (0,1,3), (0,3,2), (1,2,3)):
+ *   V^j_lk = int phi_l d_j phi_k / M_kk,  Fl_f,lk = int phi_l phi_k / M_kk,
+ *   Fn_{f,j,h},lk = int phi_l(neighbour face j, correspondence h) phi_k / M_kk,
+ * where correspondence h means own-face vertex r is neighbour-face vertex
+ * perm_h[r], perm = {012, 021, 102, 120, 201, 210}.
+ * Per face: Gp_f = (2 |S_f| / |J|) An^+, Gm_f = (2 |S_f| / |J|) An^-, the
+ * Godunov split of An = nu_x A + nu_y B + nu_z C (outward unit normal nu,
+ * physical Jacobians of the element; the flux assumes the same material on
+ * both sides of a face).  The corrector does not synchronise or allocate. */
+
+/* Basis of degree N at n_points reference points xi [n][3] -> phi [n][B]
+ * (HOST pointers). */
+stp_status stp_basis_eval(int degree, int64_t n_points, const double* xi, double* phi);
+/* Diagonal of the reference mass matrix, M [B] (HOST). */
+stp_status stp_reference_mass(int degree, double* M);
+/* Number of doubles of the corrector tables of degree N: (3 + 4 + 96) B^2
+ * (0 for a bad degree), and the tables themselves, V, Fl, Fn concatenated
+ * (HOST pointer; the caller copies them to the device for stp_correct). */
+size_t stp_corrector_tables_size(int degree);
+stp_status stp_corrector_tables(int degree, double* tables);
+/* Godunov split of one normal Jacobian An [nq][nq] (real spectrum,
+ * diagonalisable): Aplus = R max(Lambda,0) R^-1, Aminus = An - Aplus (HOST).
+ * STP_ESINGULAR if the spectrum is not real or the split is inaccurate. */
+stp_status stp_upwind_split(int n_quantities, const double* An, double* Aplus, double* Aminus);
+/* Gp, Gm [n][4][nq][nq] of a mesh (HOST): ABC [n][3][nq][nq] physical
+ * Jacobians of every element, vertices [n][4][3] its corners (local vertex
+ * order of the reference tetrahedron). */
+stp_status stp_face_operators(stp_handle handle, int n_quantities, int64_t n_elements,
+                              const double* ABC, const double* vertices, double* Gp, double* Gm);
+/* One corrector step on `hip_stream` (DEVICE pointers): tables as returned
+ * by stp_corrector_tables; star [n][3][nq][nq]; E [n][nq][nq]; Gp, Gm
+ * [n][4][nq][nq]; neighbor [n][4] (int32, the element behind each face);
+ * nb_code [n][4] (int32, 6 j + h); Qint [n][nq][B]; Q [n][nq][B] in/out.
+ * Every neighbor entry must lie in 0..n-1 and every nb_code in 0..23 (they
+ * index device arrays and are not checked).  Q must not alias Qint.
+ * STP_EINVAL if nq B exceeds 2048. */
+stp_status stp_correct(stp_handle handle, void* hip_stream, int n_quantities, int degree,
+                       int64_t n_elements, const double* tables, const double* star,
+                       const double* E, const double* Gp, const double* Gm,
+                       const int32_t* neighbor, const int32_t* nb_code, const double* Qint,
+                       double* Q);
+
 /* ---- Prediction without a caller workspace --------------------------------
  *
  * For callers that cannot allocate device memory: code under HIP graph

@@ -27,6 +27,8 @@ EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "s
             "stp_measure_peaks", "stp_static_scratch_bytes", "stp_predict_static",
             "stp_staged_workspace_size", "stp_graph_create_staged",
             "stp_workspace_size_nq", "stp_predict_nq", "stp_validate_nq",
+            "stp_basis_eval", "stp_reference_mass", "stp_corrector_tables_size", "stp_corrector_tables",
+            "stp_upwind_split", "stp_face_operators", "stp_correct",
             "stp_status_string", "stp_last_error")
 
 
@@ -76,6 +78,14 @@ def load(path: str = LIB_PATH):
     lib.stp_predict_nq.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
                                    ctypes.c_int, ctypes.c_int, vp, sz, ctypes.c_uint]
     lib.stp_validate_nq.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64, dbl, vp, vp, vp]
+    lib.stp_basis_eval.argtypes = [ctypes.c_int, i64, vp, vp]
+    lib.stp_reference_mass.argtypes = [ctypes.c_int, vp]
+    lib.stp_corrector_tables_size.argtypes = [ctypes.c_int]
+    lib.stp_corrector_tables_size.restype = sz
+    lib.stp_corrector_tables.argtypes = [ctypes.c_int, vp]
+    lib.stp_upwind_split.argtypes = [ctypes.c_int, vp, vp, vp]
+    lib.stp_face_operators.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp]
+    lib.stp_correct.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.stp_static_scratch_bytes.argtypes = []
     lib.stp_static_scratch_bytes.restype = sz
     lib.stp_predict_static.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
@@ -101,7 +111,8 @@ def load(path: str = LIB_PATH):
     lib.stp_last_error.argtypes = [vp]
     lib.stp_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("stp_status_string", "stp_last_error", "stp_static_scratch_bytes"):
+        if name not in ("stp_status_string", "stp_last_error", "stp_static_scratch_bytes",
+                        "stp_corrector_tables_size"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -256,3 +256,76 @@ def flops(degree: int):
     if st != 0:
         raise _lib.StpError(st)
     return a.value, b.value
+
+
+# ---- corrector (one ADER-DG step) --------------------------------------------
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def basis_eval(degree: int, xi):
+    """stp_basis_eval: basis values [npts, B] at reference points xi [npts, 3]."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    out = np.empty((xi.shape[0], n_modes(degree)))
+    st = _lib.load().stp_basis_eval(degree, xi.shape[0], _np_ptr(xi), _np_ptr(out))
+    if st != 0:
+        raise _lib.StpError(st)
+    return out
+
+
+def reference_mass(degree: int):
+    out = np.empty(n_modes(degree))
+    st = _lib.load().stp_reference_mass(degree, _np_ptr(out))
+    if st != 0:
+        raise _lib.StpError(st)
+    return out
+
+
+def corrector_tables(degree: int):
+    """stp_corrector_tables: (V [3,B,B], Fl [4,B,B], Fn [4,4,6,B,B]) on the host."""
+    lib = _lib.load()
+    B = n_modes(degree)
+    buf = np.empty(lib.stp_corrector_tables_size(degree))
+    st = lib.stp_corrector_tables(degree, _np_ptr(buf))
+    if st != 0:
+        raise _lib.StpError(st)
+    return buf
+
+
+def upwind_split(An):
+    An = np.ascontiguousarray(An, dtype=np.float64)
+    ap, am = np.empty_like(An), np.empty_like(An)
+    st = _lib.load().stp_upwind_split(An.shape[0], _np_ptr(An), _np_ptr(ap), _np_ptr(am))
+    if st != 0:
+        raise _lib.StpError(st, "stp_upwind_split")
+    return ap, am
+
+
+def face_operators(ABC, vertices):
+    """stp_face_operators: (Gp, Gm) [n, 4, nq, nq] from the physical Jacobians
+    ABC [n, 3, nq, nq] and the element corners [n, 4, 3] (host arrays)."""
+    h = _h()
+    ABC = np.ascontiguousarray(ABC, dtype=np.float64)
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    n, nq = ABC.shape[0], ABC.shape[-1]
+    Gp = np.empty((n, 4, nq, nq))
+    Gm = np.empty((n, 4, nq, nq))
+    h.check(h.lib.stp_face_operators(h.ptr, nq, n, _np_ptr(ABC), _np_ptr(v), _np_ptr(Gp), _np_ptr(Gm)))
+    return Gp, Gm
+
+
+def correct(degree: int, tables, star, E, Gp, Gm, neighbor, nb_code, Qint, Q, stream=None):
+    """stp_correct on device tensors; Q [n, nq, B] is updated in place."""
+    import torch
+    h = _h()
+    n, nq = int(Q.shape[0]), int(Q.shape[1])
+    if stream is None:
+        stream = torch.cuda.current_stream(Q.device)
+    for name, t, dt in (("neighbor", neighbor, torch.int32), ("nb_code", nb_code, torch.int32)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name}: contiguous {dt} expected")
+    h.check(h.lib.stp_correct(h.ptr, ctypes.c_void_p(stream.cuda_stream), nq, degree, n, _ptr(tables),
+                              _ptr(star), _ptr(E), _ptr(Gp), _ptr(Gm), _ptr(neighbor), _ptr(nb_code),
+                              _ptr(Qint), _ptr(Q)))
+    return Q

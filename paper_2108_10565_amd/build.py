@@ -84,7 +84,7 @@ def fused_object_cmd(n: int, threads: int, chunk: int, obj: str, nq: int = 13):
 
 def _objects():
     jobs = []
-    for src in ("stp_api.hip", "kernel_ref.hip", "peaks.hip", "basis.cpp"):
+    for src in ("stp_api.hip", "kernel_ref.hip", "kernel_corrector.hip", "peaks.hip", "basis.cpp", "ader_host.cpp"):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         extra = ["-x", "hip"] if src.endswith(".hip") else []
         jobs.append(([HIPCC] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj], obj))

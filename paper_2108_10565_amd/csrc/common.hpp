@@ -43,6 +43,23 @@ struct PredictArgs {
   double* Qint;          // [n][13][B] or nullptr
 };
 
+// Arguments of the corrector kernel (device pointers except the sizes).
+struct CorrectArgs {
+  int64_t n;              // elements
+  int nq, B;              // quantities, spatial modes
+  const double* tables;   // V [3][B][B], Fl [4][B][B], Fn [4][4][6][B][B]
+  const double* star;     // [n][3][nq][nq]
+  const double* E;        // [n][nq][nq]
+  const double* Gp;       // [n][4][nq][nq]
+  const double* Gm;       // [n][4][nq][nq]
+  const int32_t* neighbor;  // [n][4] element behind each face
+  const int32_t* nb_code;   // [n][4] 6 j + h: neighbour's face j, vertex correspondence h
+  const double* Qint;     // [n][nq][B]
+  double* Q;              // [n][nq][B], updated in place
+};
+hipError_t launch_corrector(const CorrectArgs& a, hipStream_t stream);
+bool corrector_fits(int nq, int B);
+
 // Bytes of workspace the mixed-precision path needs: the float residual of
 // every element between the residual and the correction kernels.
 inline size_t workspace_bytes(int nq, int N, int64_t n, int precision, int refine_steps) {

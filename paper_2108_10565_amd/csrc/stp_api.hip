@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/stp.h"
+#include "ader_host.hpp"
 #include "basis.hpp"
 #include "common.hpp"
 
@@ -537,6 +538,90 @@ stp_status stp_flops(int degree, double* paper_bound, double* executed) {
     *executed = Qn * B * T + 2 * Qn * T * T * B + 3 * 2 * T * B + 2 * 3 * Qn * Qn * T * (B - 1) +
                 2 * Qn * T * nnz;
   }
+  return STP_OK;
+}
+
+// ---- corrector ---------------------------------------------------------------
+
+stp_status stp_basis_eval(int degree, int64_t n_points, const double* xi, double* phi) {
+  if (degree < 0 || degree > STP_MAX_DEGREE) return STP_EDEGREE;
+  if (n_points < 0 || (n_points > 0 && (!xi || !phi))) return STP_EINVAL;
+  const int B = stp::n_modes(degree);
+  for (int64_t i = 0; i < n_points; ++i)
+    stp_host::eval_dubiner(degree, xi[3 * i], xi[3 * i + 1], xi[3 * i + 2], phi + i * B);
+  return STP_OK;
+}
+
+stp_status stp_reference_mass(int degree, double* M) {
+  if (degree < 0 || degree > STP_MAX_DEGREE) return STP_EDEGREE;
+  if (!M) return STP_EINVAL;
+  try {
+    const stp_host::ReferenceMatrices R = stp_host::build_reference_matrices(degree);
+    std::memcpy(M, R.M.data(), R.M.size() * sizeof(double));
+  } catch (...) {
+    return STP_ENOMEM;
+  }
+  return STP_OK;
+}
+
+size_t stp_corrector_tables_size(int degree) {
+  if (degree < 0 || degree > STP_MAX_DEGREE) return 0;
+  const size_t B = stp::n_modes(degree);
+  return (3 + 4 + 96) * B * B;
+}
+
+stp_status stp_corrector_tables(int degree, double* tables) {
+  if (degree < 0 || degree > STP_MAX_DEGREE) return STP_EDEGREE;
+  if (!tables) return STP_EINVAL;
+  try {
+    const stp_host::CorrectorTables C = stp_host::build_corrector_tables(degree);
+    double* p = tables;
+    for (const std::vector<double>* v : {&C.V, &C.Fl, &C.Fn}) {
+      std::memcpy(p, v->data(), v->size() * sizeof(double));
+      p += v->size();
+    }
+  } catch (...) {
+    return STP_ENOMEM;
+  }
+  return STP_OK;
+}
+
+stp_status stp_upwind_split(int n_quantities, const double* An, double* Aplus, double* Aminus) {
+  if (n_quantities <= 0 || !An || !Aplus || !Aminus) return STP_EINVAL;
+  std::string err;
+  return stp_host::upwind_split(n_quantities, An, Aplus, Aminus, &err) ? STP_OK : STP_ESINGULAR;
+}
+
+stp_status stp_face_operators(stp_handle handle, int n_quantities, int64_t n_elements, const double* ABC,
+                              const double* vertices, double* Gp, double* Gm) {
+  if (!handle) return STP_EINVAL;
+  handle->last_error.clear();
+  if (n_quantities <= 0 || n_elements < 0) return fail(handle, STP_EINVAL, "bad sizes");
+  if (n_elements == 0) return STP_OK;
+  if (!ABC || !vertices || !Gp || !Gm) return fail(handle, STP_EINVAL, "NULL array pointer");
+  std::string err;
+  if (!stp_host::face_operators(n_quantities, n_elements, ABC, vertices, Gp, Gm, &err))
+    return fail(handle, STP_ESINGULAR, err);
+  return STP_OK;
+}
+
+stp_status stp_correct(stp_handle handle, void* hip_stream, int n_quantities, int degree, int64_t n_elements,
+                       const double* tables, const double* star, const double* E, const double* Gp,
+                       const double* Gm, const int32_t* neighbor, const int32_t* nb_code, const double* Qint,
+                       double* Q) {
+  if (!handle) return STP_EINVAL;
+  handle->last_error.clear();
+  if (degree < 0 || degree > STP_MAX_DEGREE) return fail(handle, STP_EDEGREE, "degree out of range");
+  if (n_quantities <= 0 || n_elements < 0) return fail(handle, STP_EINVAL, "bad sizes");
+  if (n_elements == 0) return STP_OK;
+  if (!tables || !star || !E || !Gp || !Gm || !neighbor || !nb_code || !Qint || !Q)
+    return fail(handle, STP_EINVAL, "NULL array pointer");
+  const int B = stp::n_modes(degree);
+  if (!stp::corrector_fits(n_quantities, B))
+    return fail(handle, STP_EINVAL, "corrector: nq * B too large for one workgroup");
+  stp::CorrectArgs a{n_elements, n_quantities, B, tables, star, E, Gp, Gm, neighbor, nb_code, Qint, Q};
+  const hipError_t err = stp::launch_corrector(a, static_cast<hipStream_t>(hip_stream));
+  if (err != hipSuccess) return hip_fail(handle, err, "corrector launch");
   return STP_OK;
 }
 

@@ -48,6 +48,11 @@ MATERIAL_HOMOGENEOUS = dict(rho_S=2650.0, rho_F=1000.0, phi=0.2, kappa=1e-12,
                             mu_M=8e9, T=2.0)
 
 
+# material of the planar-wave convergence test (Table tab:material_convergence)
+MATERIAL_CONVERGENCE = dict(rho_S=2.5e3, rho_F=1.04e3, phi=0.2, kappa=6e-13, nu=1e-3, K_S=4.0e10,
+                            K_F=2.5e9, lambda_M=1.2e10, mu_M=1.0e10, T=3.0)
+
+
 def n_modes(N: int) -> int:
     return (N + 1) * (N + 2) * (N + 3) // 6
 
