@@ -226,6 +226,111 @@ def run_lts(args):
     print(json.dumps(out), flush=True)
 
 
+ADER_CONFIGS = {
+    # full ADER-DG steps (predictor + corrector), N=4, periodic cube of 32^3 x 5 = 163,840 elements
+    "ader_n4_m32": dict(N=4, m=32, seed=8),
+}
+
+
+def _ader_oracle_steps(args_tuple):
+    N, m, seed, steps = args_tuple
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        from oracle import ader as oader
+        from paper_2108_10565_amd import mesh as pmesh
+        M = pmesh.periodic_cube(m)
+        ABC, E = _ader_material(M.n)
+        star = wl.star_matrices(ABC[:, 0], ABC[:, 1], ABC[:, 2], M.vertices)
+        Q = np.random.default_rng(seed).standard_normal((M.n, 13, wl.n_modes(N)))
+        t = time.perf_counter()
+        corr = oader.Corrector(N, M, ABC)
+        for _ in range(steps):
+            Q = oader.ader_step(corr, star, E, Q, 1e-7)
+        return M.n * steps, time.perf_counter() - t
+
+
+def _ader_material(n):
+    mat = {k: np.array([v]) for k, v in wl.MATERIAL_CONVERGENCE.items()}
+    A, B, C, E = wl.jacobians(mat)
+    return (np.broadcast_to(np.stack([A[0], B[0], C[0]]), (n, 3, 13, 13)).copy(),
+            np.broadcast_to(E, (n, 13, 13)).copy())
+
+
+def run_ader(args):
+    """Full ADER-DG steps on a periodic cube: predictor (stp_predict) and
+    corrector (stp_correct) per step, each timed with HIP events; element
+    updates per second of the whole step, and the corrector's roofline."""
+    cfg = ADER_CONFIGS[args.workload]
+    N, m = cfg["N"], cfg["m"]
+    from paper_2108_10565_amd import mesh as pmesh
+    log(f"[bench] {args.workload}: periodic cube mesh m={m}")
+    t = time.perf_counter()
+    M = pmesh.periodic_cube(m)
+    ABC, E = _ader_material(M.n)
+    Q0 = np.random.default_rng(cfg["seed"]).standard_normal((M.n, 13, wl.n_modes(N)))
+    log(f"[bench] {M.n} elements, N={N}, generated in {time.perf_counter() - t:.1f}s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        procs = args.cpu_procs or max(1, min(8, len(os.sched_getaffinity(0))))
+        t = time.perf_counter()
+        with mp.get_context("fork").Pool(procs) as pool:
+            res = pool.map(_ader_oracle_steps, [(N, 4, cfg["seed"] + i, 1) for i in range(procs)])
+        wall = time.perf_counter() - t
+        upd = sum(r[0] for r in res)
+        cpu = {"value": upd / wall, "unit": "element updates/s", "cores": procs, "kind": "oracle",
+               "sample": f"{procs} independent oracle ADER steps (predictor + corrector, setup included) "
+                         f"on the 320-element 4^3 mesh at N={N}, one per process, 1 BLAS thread each, "
+                         f"wall {wall:.1f}s", "blas_threads_per_process": 1, **host_info()}
+        log(f"[bench] cpu baseline {cpu['value']:.1f} el/s")
+    import torch
+    from paper_2108_10565_amd import api
+    from paper_2108_10565_amd.ader import AderSolver
+    solver = AderSolver(N, M, ABC, E)
+    A, _, _, _ = wl.jacobians({k: np.array([v]) for k, v in wl.MATERIAL_CONVERGENCE.items()})
+    dt = solver.cfl_dt(float(wl.max_wave_speed(A)[0]))
+    Q = torch.from_numpy(Q0).cuda()
+    for _ in range(args.warmup):
+        solver.step(Q, dt)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for k in range(args.steps):
+        ev[k][0].record()
+        solver.predict(Q, dt)
+        ev[k][1].record()
+        solver.correct(Q)
+        ev[k][2].record()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    pred = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    corr = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    nq, B = 13, wl.n_modes(N)
+    corr_flop = 11 * (2 * nq * nq * B + 2 * nq * B * B) + 2 * nq * nq * B
+    corr_bytes = 8 * (nq * B + 4 * nq * nq + 8 * nq * nq + 2 * nq * B) + 4 * 8
+    achieved = corr_flop * M.n / (corr * 1e-3) / 1e12
+    out = {
+        "metric": "ADER-DG element updates/s (predictor + corrector per step), % roofline of the corrector",
+        "value": M.n / (ms * 1e-3), "unit": "element updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (periodic cube mesh, material of the convergence table, Q0 ~ N(0,1))",
+        "config": {"workload": args.workload, "degree": N, "elements": M.n, "mesh_subcubes": m, "dt": dt},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None, "kernel": "corrector_kernel",
+                     "flop_per_element": corr_flop, "bytes_per_element": corr_bytes,
+                     "hbm_gbs": corr_bytes * M.n / (corr * 1e-3) / 1e9},
+        "cpu_baseline": cpu,
+        "paths": {"predictor_ms": pred, "corrector_ms": corr,
+                  "predictor_el_per_s": M.n / (pred * 1e-3), "corrector_el_per_s": M.n / (corr * 1e-3)},
+    }
+    log(f"[bench] ADER step {ms:.3f} ms ({pred:.3f} predictor + {corr:.3f} corrector), "
+        f"{out['value'] / 1e6:.2f} M el/s, corrector {achieved:.2f} TFLOP/s")
+    print(json.dumps(out), flush=True)
+
+
 def rel_l2(X, Xo):
     ax = tuple(range(1, X.ndim))
     return np.sqrt(((X - Xo) ** 2).sum(ax)) / np.sqrt((Xo ** 2).sum(ax))
@@ -392,6 +497,9 @@ def main():
 
     if args.workload in wl.LTS_CONFIGS:
         run_lts(args)
+        return
+    if args.workload in ADER_CONFIGS:
+        run_ader(args)
         return
     log(f"[bench] generating workload {args.workload}")
     t = time.perf_counter()

@@ -19,7 +19,7 @@ namespace {
 constexpr int kPeakThreads = 256;
 constexpr int kPeakBlocks = 2048;        // 8 workgroups of 4 waves per compute unit
 constexpr int kChains = 16;
-constexpr int kMfmaAcc = 8;
+constexpr int kMfmaAcc = 16;
 constexpr int kFmaIters = 65536;
 constexpr int kMfmaIters = 8192;
 constexpr size_t kOutBytes = static_cast<size_t>(kPeakBlocks) * kPeakThreads * sizeof(double);
@@ -56,12 +56,11 @@ __global__ __launch_bounds__(kPeakThreads) void mfma_f64_loop(double a, double b
   out[blockIdx.x * kPeakThreads + threadIdx.x] = s;
 }
 
-struct alignas(16) d2 {
-  double x, y;
-};
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 // Streams: each thread moves kUnroll 16-byte vectors per iteration (all loads
-// issued before the stores), with streaming (non-temporal) accesses; n is a
+// issued before the stores) with streaming (non-temporal) 16-byte accesses
+// (one global_load_dwordx4 / global_store_dwordx4 per vector); n is a
 // multiple of kUnroll * threads in the grid.
 constexpr int kUnroll = 4;
 
@@ -70,26 +69,18 @@ __global__ __launch_bounds__(kPeakThreads) void copy_stream(const d2* src, d2* d
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kPeakThreads) + threadIdx.x; i < n; i += kUnroll * stride) {
     d2 v[kUnroll];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-      v[k].x = __builtin_nontemporal_load(&src[i + k * stride].x);
-      v[k].y = __builtin_nontemporal_load(&src[i + k * stride].y);
-    }
+    for (int k = 0; k < kUnroll; ++k) v[k] = __builtin_nontemporal_load(&src[i + k * stride]);
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-      __builtin_nontemporal_store(v[k].x, &dst[i + k * stride].x);
-      __builtin_nontemporal_store(v[k].y, &dst[i + k * stride].y);
-    }
+    for (int k = 0; k < kUnroll; ++k) __builtin_nontemporal_store(v[k], &dst[i + k * stride]);
   }
 }
 
 __global__ __launch_bounds__(kPeakThreads) void fill_stream(d2* dst, int64_t n, double v) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kPeakThreads;
+  const d2 vv = {v, v};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kPeakThreads) + threadIdx.x; i < n; i += kUnroll * stride) {
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-      __builtin_nontemporal_store(v, &dst[i + k * stride].x);
-      __builtin_nontemporal_store(v, &dst[i + k * stride].y);
-    }
+    for (int k = 0; k < kUnroll; ++k) __builtin_nontemporal_store(vv, &dst[i + k * stride]);
   }
 }
 
