@@ -19,7 +19,7 @@ namespace {
 constexpr int kPeakThreads = 256;
 constexpr int kPeakBlocks = 2048;        // 8 workgroups of 4 waves per compute unit
 constexpr int kChains = 16;
-constexpr int kMfmaAcc = 16;
+constexpr int kMfmaAcc = 8;
 constexpr int kFmaIters = 65536;
 constexpr int kMfmaIters = 8192;
 constexpr size_t kOutBytes = static_cast<size_t>(kPeakBlocks) * kPeakThreads * sizeof(double);
