@@ -232,7 +232,8 @@ stp_status stp_face_operators(stp_handle handle, int n_quantities, int64_t n_ele
  * nb_code [n][4] (int32, 6 j + h); Qint [n][nq][B]; Q [n][nq][B] in/out.
  * Every neighbor entry must lie in 0..n-1 and every nb_code in 0..23 (they
  * index device arrays and are not checked).  Q must not alias Qint.
- * STP_EINVAL if nq B exceeds 2048. */
+ * STP_EINVAL for a quantity count or degree whose element does not fit one
+ * workgroup's LDS (none of 6 or 13 quantities at degree 0..7). */
 stp_status stp_correct(stp_handle handle, void* hip_stream, int n_quantities, int degree,
                        int64_t n_elements, const double* tables, const double* star,
                        const double* E, const double* Gp, const double* Gm,
