@@ -94,12 +94,36 @@ def cpu_baseline(w, ids, procs):
 
 # ---------------------------------------------------------------------------
 
+def torch_copy_gbs(torch, nbytes=1 << 30, reps=5):
+    """Rate of torch's own device-to-device copy kernel (bytes read + written
+    per second) on 1 GiB, beside the library's copy stream: what another
+    implementation reaches on the same device."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def time_path(torch, api, dev, w, steps, warmup, **kw):
     """Warm up, then time `steps` calls with HIP events on torch's current
     stream (the stream the library launches on)."""
     nq = w.Q0.shape[1]
     Q = torch.empty((w.n, nq, wl.n_modes(w.N), w.N + 1), dtype=torch.float64, device="cuda")
     Qi = torch.empty((w.n, nq, wl.n_modes(w.N)), dtype=torch.float64, device="cuda")
+    # the workspace is allocated once, outside the timed calls, which then
+    # allocate nothing
+    ws = api.workspace_size(w.N, w.n, kw.get("precision", "fp64"), kw.get("refine_steps", 1), nq)
+    kw = dict(kw, workspace=torch.empty(ws, dtype=torch.uint8, device="cuda") if ws else None)
     for _ in range(warmup):
         api.predict(dev["Q0"], dev["star"], dev["E"], w.dt, w.N, Q=Q, Qint=Qi, **kw)
     torch.cuda.synchronize()
@@ -553,6 +577,7 @@ def main():
     from paper_2108_10565_amd import api
     log(f"[bench] device {torch.cuda.get_device_name(0)}")
     peaks = api.measure_peaks()
+    peaks["torch_copy_gbs"] = torch_copy_gbs(torch)
     log(f"[bench] measured ceilings: {peaks}")
     dev = {k: torch.from_numpy(getattr(w, k)).to("cuda") for k in ("Q0", "star", "E")}
     torch.cuda.synchronize()

@@ -35,7 +35,9 @@
  *
  * Errors: every entry point returns a stp_status and never aborts.  Cheap
  * argument checks are done on the host before any launch; checks that need
- * the data are in stp_validate (opt-in, synchronises).  A HIP launch
+ * the data are in stp_validate (opt-in, synchronises), and the prediction
+ * kernels report the inputs their elimination cannot take to a per-device
+ * word that stp_check_inputs reads.  A HIP launch
  * failure is reported as STP_EHIP with the HIP message in stp_last_error.
  * A handle must not be used from two host threads at once.
  */
@@ -60,10 +62,10 @@ typedef enum stp_status {
   STP_EINVAL = -1,      /* bad argument: NULL pointer with n > 0, n < 0,
                            dt <= 0 or not finite, bad enum or flags       */
   STP_EDEGREE = -2,     /* degree outside 0..STP_MAX_DEGREE               */
-  STP_ENOTUPPER = -3,   /* (stp_validate) an E has a non-zero strictly
-                           below its diagonal                             */
-  STP_ESINGULAR = -4,   /* (stp_validate) Z - dt E_pp I is singular or
-                           dt E_pp > 0 makes it nearly so                 */
+  STP_ENOTUPPER = -3,   /* (stp_validate, stp_check_inputs) an E has a
+                           non-zero strictly below its diagonal           */
+  STP_ESINGULAR = -4,   /* (stp_validate, stp_check_inputs) Z - dt E_pp I
+                           is singular or dt E_pp > 0 makes it nearly so  */
   STP_ENOMEM = -5,      /* host allocation failed                         */
   STP_EHIP = -6,        /* HIP runtime error (see stp_last_error)         */
   STP_EWORKSPACE = -7,  /* workspace smaller than stp_workspace_size      */
@@ -142,6 +144,24 @@ stp_status stp_predict(stp_handle handle, void* hip_stream, int degree,
 stp_status stp_validate(stp_handle handle, void* hip_stream, int degree,
                         int64_t n_elements, double dt, const double* star,
                         const double* E, const double* Q0);
+
+/* Input report of the prediction kernels (section "Block-wise
+ * back-substitution": the dark-blue blocks Z - dt E_pp I are inverted
+ * without pivoting, which the kernels admit for dt E_pp < 0.5, and the G
+ * coupling takes E as upper triangular).  The predict calls return before
+ * their kernels run, so they cannot fail on such data; instead every
+ * prediction kernel (stp_predict, stp_predict_nq, stp_predict_static,
+ * stp_predict_batched, graph replays; every precision and the reference
+ * kernel) ORs what it meets into a word held per device.  This call takes
+ * and clears that word of the device running `hip_stream` (atomically, in a
+ * one-thread kernel on that stream), synchronises the stream, and returns
+ * STP_ENOTUPPER (some E had a non-zero strictly below its diagonal; the
+ * kernels used only its upper part), else STP_ESINGULAR (some dt E_pp was
+ * >= 0.5; those outputs are not to be trusted), else STP_OK.  The word
+ * collects the calls of every stream and handle on the device since it was
+ * last taken; calls that are still running when it is taken report to the
+ * next call.  Not for use under graph capture. */
+stp_status stp_check_inputs(stp_handle handle, void* hip_stream);
 
 /* Reference matrices the kernels use for degree N, computed on the host by
  * Gauss quadrature in collapsed coordinates (HOST pointers, for tests):

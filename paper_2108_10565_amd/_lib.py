@@ -29,7 +29,7 @@ EXPORTED = ("stp_create", "stp_destroy", "stp_workspace_size", "stp_predict", "s
             "stp_workspace_size_nq", "stp_predict_nq", "stp_validate_nq",
             "stp_basis_eval", "stp_reference_mass", "stp_corrector_tables_size", "stp_corrector_tables",
             "stp_upwind_split", "stp_face_operators", "stp_correct",
-            "stp_status_string", "stp_last_error")
+            "stp_check_inputs", "stp_status_string", "stp_last_error")
 
 
 class StpBatch(ctypes.Structure):
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH):
     lib.stp_predict.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,
                                 ctypes.c_int, ctypes.c_int, vp, sz, ctypes.c_uint]
     lib.stp_validate.argtypes = [vp, vp, ctypes.c_int, i64, dbl, vp, vp, vp]
+    lib.stp_check_inputs.argtypes = [vp, vp]
     lib.stp_workspace_size_nq.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(sz)]
     lib.stp_predict_nq.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, i64, dbl, vp, vp, vp, vp, vp,

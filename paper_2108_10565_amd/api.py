@@ -38,7 +38,7 @@ def workspace_size(degree: int, n: int, precision: str = "fp64", refine_steps: i
 
 def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine_steps: int = 1,
             Q=None, Qint=None, with_qint: bool = True, reference_kernel: bool = False,
-            stream=None, mfma_float_chain: bool = False):
+            stream=None, mfma_float_chain: bool = False, workspace=None):
     """Space-time DOFs Q [n,nq,B,T] and time-integrated DOFs Qint [n,nq,B].
 
     Q0 [n,nq,B], star [n,3,nq,nq], E [n,nq,nq]: float64, contiguous, on the
@@ -46,7 +46,10 @@ def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine
     from Q0 (stp_predict_nq).  Outputs are allocated here unless passed in.  The call
     is asynchronous on ``stream`` (default: torch's current stream).
     ``mfma_float_chain`` selects the matrix-core float32 chain
-    (STP_FLAG_MFMA_FLOAT_CHAIN) for precision="fp32_refine"."""
+    (STP_FLAG_MFMA_FLOAT_CHAIN) for precision="fp32_refine".  ``workspace``
+    (a contiguous uint8 cuda tensor of at least workspace_size() bytes)
+    is used instead of allocating one, so that a call with Q, Qint and
+    workspace passed in allocates nothing."""
     import torch
     h = _h()
     n = _check_inputs(Q0, star, E, degree)
@@ -56,8 +59,13 @@ def predict(Q0, star, E, dt: float, degree: int, precision: str = "fp64", refine
         Q = torch.empty((n, nq, B, T), dtype=torch.float64, device=Q0.device)
     if Qint is None and with_qint:
         Qint = torch.empty((n, nq, B), dtype=torch.float64, device=Q0.device)
-    ws = workspace_size(degree, n, precision, refine_steps, nq)
-    work = torch.empty(ws, dtype=torch.uint8, device=Q0.device) if ws else None
+    if workspace is not None:
+        if workspace.dtype != torch.uint8 or not workspace.is_contiguous() or workspace.device != Q0.device:
+            raise ValueError("workspace: expected a contiguous uint8 tensor on the device of Q0")
+        work, ws = workspace, workspace.numel()
+    else:
+        ws = workspace_size(degree, n, precision, refine_steps, nq)
+        work = torch.empty(ws, dtype=torch.uint8, device=Q0.device) if ws else None
     if stream is None:
         stream = torch.cuda.current_stream(Q0.device)
     flags = (_lib.STP_FLAG_REFERENCE_KERNEL if reference_kernel else 0) | \
@@ -235,6 +243,18 @@ def validate(Q0, star, E, dt: float, degree: int, stream=None) -> None:
         stream = torch.cuda.current_stream(Q0.device)
     h.check(h.lib.stp_validate_nq(h.ptr, ctypes.c_void_p(stream.cuda_stream), int(Q0.shape[1]), degree,
                                   int(Q0.shape[0]), float(dt), _ptr(star), _ptr(E), _ptr(Q0)))
+
+
+def check_inputs(stream=None) -> None:
+    """stp_check_inputs: takes the device's report of inputs the prediction
+    kernels met and could not take (dt E_pp >= 0.5, E not upper triangular)
+    since the last check; raises StpError (ESINGULAR / ENOTUPPER) if there
+    were any.  Synchronises ``stream`` (default: torch's current stream)."""
+    import torch
+    h = _h()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h.check(h.lib.stp_check_inputs(h.ptr, ctypes.c_void_p(stream.cuda_stream)))
 
 
 def reference_matrices(degree: int):

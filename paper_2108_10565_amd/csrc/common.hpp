@@ -41,7 +41,13 @@ struct PredictArgs {
   const double* Q0;      // [n][13][B]
   double* Q;             // [n][13][B][T]
   double* Qint;          // [n][13][B] or nullptr
+  unsigned* status;      // device word the kernels OR input conditions into (kInput*), or nullptr
 };
+
+// Input conditions the prediction kernels report (they run without pivoting
+// and take E as upper triangular; section "Block-wise back-substitution").
+constexpr unsigned kInputSingular = 1u;  // some dt E_pp >= 0.5
+constexpr unsigned kInputNotUpper = 2u;  // a non-zero below the diagonal of some E
 
 // Arguments of the corrector kernel (device pointers except the sizes).
 struct CorrectArgs {

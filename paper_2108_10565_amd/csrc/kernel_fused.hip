@@ -368,10 +368,15 @@ struct LaneSetup {
   __device__ __forceinline__ void run(Shared<N, R>& sh, const PredictArgs& a, int64_t e0, int nloc, int tid,
                                       int es, int p, int u, bool active, int cb) {
     constexpr int kThreads = C::kThreads, T = C::T;
+    unsigned bad = 0;  // input conditions the elimination without pivoting cannot take
     for (int i = tid; i < C::kSlots * kNQ * kNQ; i += kThreads) {
       const int r = (i / kNQ) % kNQ, c = i % kNQ;
-      (&sh.G[0][0][0])[i] = (i < nloc * kNQ * kNQ && c >= r) ? a.dt * a.E[e0 * (kNQ * kNQ) + i] : 0.0;
+      const double v = i < nloc * kNQ * kNQ ? a.dt * a.E[e0 * (kNQ * kNQ) + i] : 0.0;
+      if (c < r && v != 0.0) bad |= kInputNotUpper;
+      if (c == r && v >= 0.5) bad |= kInputSingular;
+      (&sh.G[0][0][0])[i] = c >= r ? v : 0.0;
     }
+    if (bad && a.status) atomicOr(a.status, bad);
     for (int i = tid; i < C::kSlots * 3 * kNQ * kNQ; i += kThreads)
       (&sh.u.A[0][0][0][0])[i] = i < nloc * 3 * kNQ * kNQ ? a.dt * a.star[e0 * (3 * kNQ * kNQ) + i] : 0.0;
     if (tid == 0) sh.maxlevel = 0;

@@ -64,10 +64,15 @@ __global__ __launch_bounds__(kRefThreads) void stp_reference_kernel(PredictArgs 
     const double* Q0 = a.Q0 + e * (kNQ * B);
     double* Q = a.Q + e * (kNQ * B * T);
     for (int t = tid; t < 3 * kNQ * kNQ; t += kRefThreads) s.A[t] = a.dt * star[t];
+    unsigned bad = 0;
     for (int t = tid; t < kNQ * kNQ; t += kRefThreads) {
       const int r = t / kNQ, c = t % kNQ;
-      s.Es[t] = (c >= r) ? a.dt * E[t] : 0.0;
+      const double v = a.dt * E[t];
+      if (c < r && v != 0.0) bad |= kInputNotUpper;
+      if (c == r && v >= 0.5) bad |= kInputSingular;
+      s.Es[t] = (c >= r) ? v : 0.0;
     }
+    if (bad && a.status) atomicOr(a.status, bad);
     __syncthreads();
     // (Z - E*_pp I)^-1 for every quantity, one thread each
     if (tid < kNQ) {

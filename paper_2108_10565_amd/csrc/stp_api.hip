@@ -96,12 +96,58 @@ stp_status check_predict(stp_handle h, int degree, int64_t n, double dt, const d
   return STP_OK;
 }
 
+// Per-device words of the input report: [0] collects what the prediction
+// kernels OR into it (stp::kInputSingular, stp::kInputNotUpper), [1]
+// receives it when stp_check_inputs takes it.  Host code uses only the
+// device address from hipGetSymbolAddress (each device holds its own copy).
+static __device__ __align__(64) unsigned input_status[2];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_status_mutex;
+unsigned* g_status_ptr[kMaxDevices] = {};
+
+// Device that runs `stream` (the NULL stream: the current device), or -1.
+int stream_device(hipStream_t stream) {
+  if (stream) {
+    hipDevice_t d = 0;
+    return hipStreamGetDevice(stream, &d) == hipSuccess ? static_cast<int>(d) : -1;
+  }
+  int cur = -1;
+  return hipGetDevice(&cur) == hipSuccess ? cur : -1;
+}
+
+// Device address of `input_status` on device `dev`, taken on first use with
+// `dev` current; nullptr if it cannot be had (the kernels then report nothing).
+unsigned* status_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_status_mutex);
+  if (!g_status_ptr[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    void* p = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(input_status));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (err != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_status_ptr[dev] = static_cast<unsigned*>(p);
+  }
+  return g_status_ptr[dev];
+}
+
+__global__ void take_status_kernel(unsigned* s) { s[1] = atomicExch(&s[0], 0u); }
+
 // Launches one checked prediction request on `stream`.
 stp_status launch_predict(stp_handle h, hipStream_t stream, int degree, int64_t n, double dt, const double* star,
                           const double* E, const double* Q0, double* Q, double* Qint, stp_precision precision,
                           int refine_steps, void* workspace, unsigned flags, int nq = STP_NQ) {
   if (n == 0) return STP_OK;
-  stp::PredictArgs a{n, dt, star, E, Q0, Q, Qint};
+  stp::PredictArgs a{n, dt, star, E, Q0, Q, Qint, status_address(stream_device(stream))};
   hipError_t err;
   if (flags & STP_FLAG_REFERENCE_KERNEL)
     err = stp::launch_reference_kernel(degree, a, stream);
@@ -145,7 +191,6 @@ stp_status launch_batches(stp_handle h, hipStream_t stream, int n_batches, const
 constexpr size_t kScratchBytes = size_t(256) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
-constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
 void* g_scratch_ptr[kMaxDevices] = {};
 
@@ -218,7 +263,10 @@ stp_status stp_predict_static(stp_handle handle, void* hip_stream, int degree, i
 stp_status stp_create(stp_handle* handle) {
   if (!handle) return STP_EINVAL;
   *handle = new (std::nothrow) stp_handle_s();
-  return *handle ? STP_OK : STP_ENOMEM;
+  if (!*handle) return STP_ENOMEM;
+  // the current device's input-report address, outside any graph capture
+  (void)status_address(stream_device(nullptr));
+  return STP_OK;
 }
 
 stp_status stp_destroy(stp_handle handle) {
@@ -315,6 +363,7 @@ stp_status stp_graph_create(stp_handle handle, void* hip_stream, int n_batches, 
   stp_graph g = new (std::nothrow) stp_graph_s();
   if (!g) return fail(handle, STP_ENOMEM, "out of host memory");
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  (void)status_address(stream_device(stream));  // taken before the capture
   hipError_t err = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
   if (err != hipSuccess) {
     delete g;
@@ -396,6 +445,7 @@ stp_status stp_graph_create_staged(stp_handle handle, void* hip_stream, int n_st
   if (err == hipSuccess) err = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
   for (int i = 0; i < kBranches && err == hipSuccess; ++i) err = hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming);
   bool capturing = false;
+  (void)status_address(stream_device(s0));  // taken before the capture
   if (err == hipSuccess) {
     err = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
     capturing = err == hipSuccess;
@@ -499,6 +549,24 @@ stp_status stp_validate_nq(stp_handle handle, void* hip_stream, int n_quantities
 stp_status stp_validate(stp_handle handle, void* hip_stream, int degree, int64_t n_elements, double dt,
                         const double* star, const double* E, const double* Q0) {
   return stp_validate_nq(handle, hip_stream, STP_NQ, degree, n_elements, dt, star, E, Q0);
+}
+
+stp_status stp_check_inputs(stp_handle handle, void* hip_stream) {
+  if (!handle) return STP_EINVAL;
+  handle->last_error.clear();
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  unsigned* ds = status_address(stream_device(stream));
+  if (!ds) return fail(handle, STP_EHIP, "input report word of the stream's device unavailable");
+  unsigned hs = 0;
+  hipLaunchKernelGGL(take_status_kernel, dim3(1), dim3(1), 0, stream, ds);
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = hipMemcpyAsync(&hs, ds + 1, sizeof(unsigned), hipMemcpyDeviceToHost, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  if (err != hipSuccess) return hip_fail(handle, err, "check_inputs");
+  if (hs & stp::kInputNotUpper)
+    return fail(handle, STP_ENOTUPPER, "a predict call met an E with a non-zero below its diagonal");
+  if (hs & stp::kInputSingular) return fail(handle, STP_ESINGULAR, "a predict call met dt * E_pp >= 0.5");
+  return STP_OK;
 }
 
 stp_status stp_reference_matrices(stp_handle handle, int degree, double* Z, double* Sinv_w, double* Khat) {

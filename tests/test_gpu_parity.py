@@ -142,7 +142,7 @@ def test_empty_and_no_qint(kernel):
     _check(Q.cpu().numpy(), None, Xo, Io)
 
 
-@pytest.mark.parametrize("kernel", ["reference", "fused_fp64"])
+@pytest.mark.parametrize("kernel", ["reference", "fused_fp64", "fused_fp32_refine2", "mfma_fp32_refine2"])
 def test_deterministic(kernel):
     _say(f"[gpu] deterministic kernel={kernel}")
     w = wl.make_small(6, 9, seed=9)
@@ -165,6 +165,51 @@ def test_validate_reports_bad_inputs():
     E = w.E.copy(); E[0, 4, 4] = 10.0 / w.dt
     with pytest.raises(StpError, match="ESINGULAR"):
         api.validate(_dev(w.Q0), _dev(w.star), _dev(E), w.dt, 3)
+
+
+@pytest.mark.parametrize("kernel", ["reference", "fused_fp64", "fused_fp32_refine2"])
+def test_predict_reports_unfit_inputs(kernel):
+    """The prediction kernels report what their elimination without pivoting
+    cannot take (dt E_pp >= 0.5) and an E with a non-zero below its diagonal
+    through stp_check_inputs; fit inputs report nothing, and taking the
+    report clears it."""
+    _say(f"[gpu] input report kernel={kernel}")
+    from paper_2108_10565_amd import StpError
+    w = wl.make_small(3, 4, seed=12)
+    try:
+        api.check_inputs()  # take whatever an earlier call left
+    except StpError:
+        pass
+    _run(w, **KERNELS[kernel])
+    api.check_inputs()
+    E = w.E.copy(); E[1, 11, 11] = 0.6 / w.dt
+    api.predict(_dev(w.Q0), _dev(w.star), _dev(E), w.dt, 3, **KERNELS[kernel])
+    with pytest.raises(StpError, match="ESINGULAR"):
+        api.check_inputs()
+    api.check_inputs()
+    E = w.E.copy(); E[2, 5, 1] = 1.0
+    api.predict(_dev(w.Q0), _dev(w.star), _dev(E), w.dt, 3, **KERNELS[kernel])
+    with pytest.raises(StpError, match="ENOTUPPER"):
+        api.check_inputs()
+    _run(w, **KERNELS[kernel])
+    api.check_inputs()
+
+
+def test_caller_workspace_is_used_as_is():
+    """predict() with the caller's workspace gives bitwise the results of a
+    call that allocates its own."""
+    _say("[gpu] caller workspace")
+    w = wl.make_small(6, 7, seed=13)
+    Q1, I1 = _run(w, **KERNELS["fused_fp32_refine2"])
+    ws = api.workspace_size(6, w.n, "fp32_refine", 2)
+    work = torch.full((ws + 64,), 255, dtype=torch.uint8, device="cuda")
+    Q, Qi = api.predict(_dev(w.Q0), _dev(w.star), _dev(w.E), w.dt, 6, workspace=work, **KERNELS["fused_fp32_refine2"])
+    torch.cuda.synchronize()
+    assert np.array_equal(Q.cpu().numpy(), Q1) and np.array_equal(Qi.cpu().numpy(), I1)
+    from paper_2108_10565_amd import StpError
+    with pytest.raises(StpError, match="EWORKSPACE"):
+        api.predict(_dev(w.Q0), _dev(w.star), _dev(w.E), w.dt, 6, workspace=work[:ws - 8],
+                    **KERNELS["fused_fp32_refine2"])
 
 
 def test_kernels_agree_with_each_other():
