@@ -252,8 +252,8 @@ stp_status stp_face_operators(stp_handle handle, int n_quantities, int64_t n_ele
  * nb_code [n][4] (int32, 6 j + h); Qint [n][nq][B]; Q [n][nq][B] in/out.
  * Every neighbor entry must lie in 0..n-1 and every nb_code in 0..23 (they
  * index device arrays and are not checked).  Q must not alias Qint.
- * STP_EINVAL for a quantity count or degree whose element does not fit one
- * workgroup's LDS (none of 6 or 13 quantities at degree 0..7). */
+ * STP_EINVAL for a quantity count other than 13 or 6 (the kernels are
+ * compiled per quantity count and degree). */
 stp_status stp_correct(stp_handle handle, void* hip_stream, int n_quantities, int degree,
                        int64_t n_elements, const double* tables, const double* star,
                        const double* E, const double* Gp, const double* Gm,
@@ -375,8 +375,8 @@ typedef struct stp_peaks {
   double fp64_valu_tflops;   /* v_fma_f64 over all compute units            */
   double fp32_valu_tflops;   /* v_fma_f32 (no packed float32 instructions)  */
   double fp64_mfma_tflops;   /* 16x16x4 float64 matrix-core instructions    */
-  double hbm_copy_gbs;       /* bytes read + bytes written per second       */
-  double hbm_write_gbs;      /* bytes written per second                    */
+  double hbm_copy_gbs;       /* bytes read + bytes written per second (best of grid sizes and access kinds) */
+  double hbm_write_gbs;      /* bytes written per second (same)             */
 } stp_peaks;
 
 stp_status stp_measure_peaks(stp_handle handle, void* hip_stream, void* scratch, size_t scratch_bytes,

@@ -7,7 +7,8 @@
 // (runtime a, b, trip count), so the loop cannot be folded and the chains
 // hide the FMA latency; one result per thread is stored so nothing is dead.
 // Matrix cores: independent accumulators of the 16x16x4 float64 MFMA.
-// Streams: grid-stride copy and fill of 16-byte vectors through HBM.
+// Streams: grid-stride copy and fill of 16-byte vectors through HBM (best of
+// three grid sizes, streaming and ordinary accesses).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -59,28 +60,37 @@ __global__ __launch_bounds__(kPeakThreads) void mfma_f64_loop(double a, double b
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 // Streams: each thread moves kUnroll 16-byte vectors per iteration (all loads
-// issued before the stores) with streaming (non-temporal) 16-byte accesses
-// (one global_load_dwordx4 / global_store_dwordx4 per vector); n is a
-// multiple of kUnroll * threads in the grid.
+// issued before the stores; one global_load_dwordx4 / global_store_dwordx4
+// per vector), as streaming (non-temporal) or ordinary accesses; n is a
+// multiple of kUnroll * threads in the grid.  The rate reported is the best
+// of a few grid sizes and both access kinds.
 constexpr int kUnroll = 4;
 
+template <bool kStreaming>
 __global__ __launch_bounds__(kPeakThreads) void copy_stream(const d2* src, d2* dst, int64_t n) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kPeakThreads;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kPeakThreads) + threadIdx.x; i < n; i += kUnroll * stride) {
     d2 v[kUnroll];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) v[k] = __builtin_nontemporal_load(&src[i + k * stride]);
+    for (int k = 0; k < kUnroll; ++k) v[k] = kStreaming ? __builtin_nontemporal_load(&src[i + k * stride]) : src[i + k * stride];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) __builtin_nontemporal_store(v[k], &dst[i + k * stride]);
+    for (int k = 0; k < kUnroll; ++k) {
+      if constexpr (kStreaming) __builtin_nontemporal_store(v[k], &dst[i + k * stride]);
+      else dst[i + k * stride] = v[k];
+    }
   }
 }
 
+template <bool kStreaming>
 __global__ __launch_bounds__(kPeakThreads) void fill_stream(d2* dst, int64_t n, double v) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kPeakThreads;
   const d2 vv = {v, v};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kPeakThreads) + threadIdx.x; i < n; i += kUnroll * stride) {
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) __builtin_nontemporal_store(vv, &dst[i + k * stride]);
+    for (int k = 0; k < kUnroll; ++k) {
+      if constexpr (kStreaming) __builtin_nontemporal_store(vv, &dst[i + k * stride]);
+      else dst[i + k * stride] = vv;
+    }
   }
 }
 
@@ -130,16 +140,32 @@ extern "C" stp_status stp_measure_peaks(stp_handle handle, void* hip_stream, voi
   const double tm = time_ms(stream, 3, [&] {
     hipLaunchKernelGGL(mfma_f64_loop, grid, block, 0, stream, 1e-3, 1e-3, kMfmaIters, out64);
   });
-  // streams over the buffer past the FMA results, split in two halves
-  const dim3 sgrid(4096);
-  const int64_t unit = static_cast<int64_t>(kUnroll) * sgrid.x * kPeakThreads;   // vectors per grid sweep
+  // streams over the buffer past the FMA results, split in two halves; the
+  // grid sizes (workgroups of 256) all divide the vector count
+  constexpr int kGrids[3] = {4096, 1024, 512};
+  const int64_t unit = static_cast<int64_t>(kUnroll) * kGrids[0] * kPeakThreads;   // vectors per largest sweep
   const int64_t n = static_cast<int64_t>((scratch_bytes - kOutBytes) / 2 / sizeof(d2)) / unit * unit;
   d2* half0 = reinterpret_cast<d2*>(static_cast<char*>(scratch) + kOutBytes);
   d2* half1 = half0 + n;
-  const double tf = time_ms(stream, 5, [&] { hipLaunchKernelGGL(fill_stream, sgrid, block, 0, stream, half0, n, 1.0); });
-  const double tc = time_ms(stream, 5, [&] {
-    hipLaunchKernelGGL(copy_stream, sgrid, block, 0, stream, static_cast<const d2*>(half0), half1, n);
-  });
+  double tf = 1e30, tc = 1e30;
+  bool stream_error = false;
+  for (int gi = 0; gi < 3; ++gi) {
+    const dim3 sgrid(kGrids[gi]);
+    for (int nt = 0; nt < 2; ++nt) {
+      const double f = time_ms(stream, 5, [&] {
+        if (nt) hipLaunchKernelGGL(fill_stream<true>, sgrid, block, 0, stream, half0, n, 1.0);
+        else hipLaunchKernelGGL(fill_stream<false>, sgrid, block, 0, stream, half0, n, 1.0);
+      });
+      const double c = time_ms(stream, 5, [&] {
+        if (nt) hipLaunchKernelGGL(copy_stream<true>, sgrid, block, 0, stream, static_cast<const d2*>(half0), half1, n);
+        else hipLaunchKernelGGL(copy_stream<false>, sgrid, block, 0, stream, static_cast<const d2*>(half0), half1, n);
+      });
+      if (f <= 0 || c <= 0) stream_error = true;
+      tf = f < tf ? f : tf;
+      tc = c < tc ? c : tc;
+    }
+  }
+  if (stream_error) tf = tc = -1.0;
   if (t64 <= 0 || t32 <= 0 || tm <= 0 || tf <= 0 || tc <= 0) {
     (void)hipGetLastError();
     return STP_EHIP;

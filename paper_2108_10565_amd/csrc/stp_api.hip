@@ -686,7 +686,8 @@ stp_status stp_correct(stp_handle handle, void* hip_stream, int n_quantities, in
     return fail(handle, STP_EINVAL, "NULL array pointer");
   const int B = stp::n_modes(degree);
   if (!stp::corrector_fits(n_quantities, B))
-    return fail(handle, STP_EINVAL, "corrector: nq * B too large for one workgroup");
+    return fail(handle, STP_EINVAL, "corrector: kernels for 13 or 6 quantities only, got " +
+                                        std::to_string(n_quantities));
   stp::CorrectArgs a{n_elements, n_quantities, B, tables, star, E, Gp, Gm, neighbor, nb_code, Qint, Q};
   const hipError_t err = stp::launch_corrector(a, static_cast<hipStream_t>(hip_stream));
   if (err != hipSuccess) return hip_fail(handle, err, "corrector launch");

@@ -78,6 +78,15 @@ def test_corrector_matches_oracle(system, N):
     parity.check(Qd.cpu().numpy(), ref, TOL, "Q^{n+1}", say=_say)
 
 
+@pytest.mark.parametrize("system,N", [("poro_heterogeneous", 0), ("poro_heterogeneous", 3),
+                                      ("poro_heterogeneous", 6), ("poro_heterogeneous", 7),
+                                      ("maxwell", 0), ("maxwell", 6)])
+def test_corrector_other_degrees(system, N):
+    """The corrector's other compiled degrees, among them the tiles whose
+    terms run in several groups (N = 6, 7 with 13 quantities)."""
+    test_corrector_matches_oracle(system, N)
+
+
 def test_full_step_matches_oracle():
     """One ADER-DG step (predictor + corrector) on the GPU against the
     oracle's predictor + corrector, N = 2, plane-wave initial data."""
