@@ -160,6 +160,7 @@ struct Shared {
   double dr[C::kThreads][C::T];             // per lane: row of Zinv_o G_op Zinv_p (closure coupling)
   int level[C::kSlots][kNQ];
   int maxlevel;
+  unsigned flags;
   union {
     double A[C::kSlots][3][kNQ][kNQ];       // setup only: A^{j*} = dt A^j
     struct {
@@ -352,9 +353,10 @@ constexpr int kInit = 0;     // b = Q0 (S^-1 w); Q <- X
 constexpr int kCorrect = 1;  // b = residual (float workspace); Q <- Q + X
 
 // Per-lane setup shared by the solve and residual kernels: stages E* and
-// A^{j*} of the group, derives the dependency levels of the strict upper part
-// G of E*, row u of (Z - E*_pp I)^-1 (to LDS), the sparse star row, the G
-// coupling of the lane's quantity and the closure row dr (to LDS).
+// A^{j*} of the group, then per lane the sparse star row, the G coupling of
+// the lane's quantity, row u of (Z - E*_pp I)^-1 (to LDS) and the closure row
+// dr (to LDS); the dependency levels of the strict upper part G of E* only
+// when some coupling is not of the closure form.
 template <int N, typename R>
 struct LaneSetup {
   using C = Cfg<N>;
@@ -369,77 +371,50 @@ struct LaneSetup {
                                       int es, int p, int u, bool active, int cb) {
     constexpr int kThreads = C::kThreads, T = C::T;
     unsigned bad = 0;  // input conditions the elimination without pivoting cannot take
-    for (int i = tid; i < C::kSlots * kNQ * kNQ; i += kThreads) {
+    // E and the star matrices of the group: every load is issued before the
+    // first LDS store, so the group waits for one memory latency
+    constexpr int kEIt = (C::kSlots * kNQ * kNQ + kThreads - 1) / kThreads;
+    constexpr int kAIt = (C::kSlots * 3 * kNQ * kNQ + kThreads - 1) / kThreads;
+    double ev[kEIt], av[kAIt];
+#pragma unroll
+    for (int k = 0; k < kEIt; ++k) {
+      const int i = tid + k * kThreads;
+      ev[k] = i < nloc * kNQ * kNQ ? a.E[e0 * (kNQ * kNQ) + i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kAIt; ++k) {
+      const int i = tid + k * kThreads;
+      av[k] = i < nloc * 3 * kNQ * kNQ ? a.star[e0 * (3 * kNQ * kNQ) + i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kEIt; ++k) {
+      const int i = tid + k * kThreads;
       const int r = (i / kNQ) % kNQ, c = i % kNQ;
-      const double v = i < nloc * kNQ * kNQ ? a.dt * a.E[e0 * (kNQ * kNQ) + i] : 0.0;
+      const double v = a.dt * ev[k];
       if (c < r && v != 0.0) bad |= kInputNotUpper;
       if (c == r && v >= 0.5) bad |= kInputSingular;
-      (&sh.G[0][0][0])[i] = c >= r ? v : 0.0;
+      if (i < C::kSlots * kNQ * kNQ) (&sh.G[0][0][0])[i] = c >= r ? v : 0.0;
     }
     if (bad && a.status) atomicOr(a.status, bad);
-    for (int i = tid; i < C::kSlots * 3 * kNQ * kNQ; i += kThreads)
-      (&sh.u.A[0][0][0][0])[i] = i < nloc * 3 * kNQ * kNQ ? a.dt * a.star[e0 * (3 * kNQ * kNQ) + i] : 0.0;
-    if (tid == 0) sh.maxlevel = 0;
+#pragma unroll
+    for (int k = 0; k < kAIt; ++k) {
+      const int i = tid + k * kThreads;
+      if (i < C::kSlots * 3 * kNQ * kNQ) (&sh.u.A[0][0][0][0])[i] = a.dt * av[k];
+    }
+    if (tid == 0) {
+      sh.maxlevel = 0;
+      sh.flags = 0;
+    }
     __syncthreads();
-    // dependency levels, one thread per element
-    if (tid < nloc) {
-      int lev[kNQ];
-      int mx = 0;
-#pragma unroll
-      for (int o = kNQ - 1; o >= 0; --o) {
-        int l = 0;
-#pragma unroll
-        for (int q = o + 1; q < kNQ; ++q)
-          if (sh.G[tid][o][q] != 0.0 && lev[q] + 1 > l) l = lev[q] + 1;
-        lev[o] = l;
-        sh.level[tid][o] = l;
-        mx = l > mx ? l : mx;
-      }
-      atomicMax(&sh.maxlevel, mx);
-    }
-    // row u of (Z - E*_pp I)^-1
-    double zr[T];
-    {
-      double e_u[T];
-#pragma unroll
-      for (int v = 0; v < T; ++v) e_u[v] = (v == u) ? 1.0 : 0.0;
-      zt_solve<T>(sh.G[es][p][p], e_u, zr);
-#pragma unroll
-      for (int v = 0; v < T; ++v) sh.zr[tid][v] = zr[v];
-    }
-    // sparse row p of the three star matrices
-    bool overflow = false;
-    {
-      int cnt = 0;
-#pragma unroll
-      for (int k = 0; k < kStarNnz; ++k) {
-        sa0[k] = sa1[k] = sa2[k] = R(0);
-        sq[k] = cb + u;
-      }
-#pragma unroll
-      for (int q = 0; q < kNQ; ++q) {
-        const double v0 = sh.u.A[es][0][p][q], v1 = sh.u.A[es][1][p][q], v2 = sh.u.A[es][2][p][q];
-        if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
-#pragma unroll
-          for (int k = 0; k < kStarNnz; ++k)
-            if (k == cnt) {
-              sa0[k] = static_cast<R>(v0);
-              sa1[k] = static_cast<R>(v1);
-              sa2[k] = static_cast<R>(v2);
-              sq[k] = C::blk(es, q) + u;
-            }
-          ++cnt;
-        }
-      }
-      overflow = active && cnt > kStarNnz;
-    }
-    // G coupling of this lane's quantity
+    // G coupling of this lane's quantity (the first non-zero right of the
+    // diagonal and their count), and whether that partner couples further
     gcount = 0;
     gp = p;
     gcoef = 0.0;
-    for (int q = p + 1; q < kNQ; ++q) {
+#pragma unroll
+    for (int q = 1; q < kNQ; ++q) {
       const double gq = sh.G[es][p][q];
-      if (gq != 0.0) {
+      if (q > p && gq != 0.0) {
         if (gcount == 0) {
           gcoef = gq;
           gp = q;
@@ -447,32 +422,113 @@ struct LaneSetup {
         ++gcount;
       }
     }
-    // uniform over the workgroup: scalar branches, no exec masking.  This
-    // barrier also orders the reads of A before the chunk buffers (which share
-    // its storage) are written.
-    dense_star = __builtin_amdgcn_readfirstlane(__syncthreads_or(overflow)) != 0;
-    maxlevel = sh.maxlevel;
-    mylevel = active ? sh.level[es][p] : 0;
-    const int gp_level = active ? sh.level[es][gp] : 0;
-    // closure form of the coupling when every coupled quantity couples to one
-    // quantity that itself is uncoupled (the poroelastic case):
-    //   X_o = Zinv_o (b_o + g X_p) = zr . b_o + dr . b_p,
-    //   dr = g * (row of Zinv_o) * Zinv_p, i.e. (Z - E*_pp I)^T dr = g zr
-    closure = __builtin_amdgcn_readfirstlane(
-                  __syncthreads_and(!active || (gcount <= 1 && (gcount == 0 || gp_level == 0)))) != 0;
+    bool partner_coupled = false;
+#pragma unroll
+    for (int q = 1; q < kNQ; ++q)
+      partner_coupled = partner_coupled || (q > gp && sh.G[es][gp][q] != 0.0);
+    // sparse row p of the three star matrices: the columns with a non-zero
+    // in any direction, in ascending order (a bit mask, consumed lowest bit
+    // first)
+    unsigned mask = 0;
+#pragma unroll
+    for (int q = 0; q < kNQ; ++q) {
+      const double v0 = sh.u.A[es][0][p][q], v1 = sh.u.A[es][1][p][q], v2 = sh.u.A[es][2][p][q];
+      if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) mask |= 1u << q;
+    }
+    const bool overflow = active && __builtin_popcount(mask) > kStarNnz;
+#pragma unroll
+    for (int k = 0; k < kStarNnz; ++k) {
+      const bool live = mask != 0;
+      const int q = live ? __builtin_ctz(mask) : p;
+      mask &= mask - 1;
+      const double v0 = sh.u.A[es][0][p][q], v1 = sh.u.A[es][1][p][q], v2 = sh.u.A[es][2][p][q];
+      sa0[k] = live ? static_cast<R>(v0) : R(0);
+      sa1[k] = live ? static_cast<R>(v1) : R(0);
+      sa2[k] = live ? static_cast<R>(v2) : R(0);
+      sq[k] = (live ? C::blk(es, q) : cb) + u;
+    }
+    // row u of (Z - E*_pp I)^-1.  Without a diagonal source it is row u of
+    // Z^-1, which has two non-zeros (generated table); otherwise it comes from
+    // an elimination, done only by waves holding such a lane.
+    {
+      const double z = sh.G[es][p][p];
+      using ZS = stp_gen::ZinvSparse<N>;
+      double zr[T];
+#pragma unroll
+      for (int v = 0; v < T; ++v)
+        zr[v] = (ZS::col[2 * u] == v ? ZS::val[2 * u] : 0.0) + (ZS::col[2 * u + 1] == v ? ZS::val[2 * u + 1] : 0.0);
+      if (__builtin_amdgcn_ballot_w64(z != 0.0) != 0) {
+        double e_u[T], zs[T];
+#pragma unroll
+        for (int v = 0; v < T; ++v) e_u[v] = (v == u) ? 1.0 : 0.0;
+        zt_solve<T>(z, e_u, zs);
+        if (z != 0.0) {
+#pragma unroll
+          for (int v = 0; v < T; ++v) zr[v] = zs[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < T; ++v) sh.zr[tid][v] = zr[v];
+    }
+    // one barrier for the workgroup-uniform flags (scalar branches, no exec
+    // masking); it also orders the reads of A before the chunk buffers (which
+    // share its storage) are written, and the rows of Zinv before their reads
+    // below.  The closure form of the coupling applies when every coupled
+    // quantity couples to one quantity that itself is uncoupled (the
+    // poroelastic case).
+    {
+      const unsigned f = (overflow ? 1u : 0u) | ((active && (gcount > 1 || (gcount == 1 && partner_coupled))) ? 2u : 0u);
+      if (f) atomicOr(&sh.flags, f);
+    }
+    __syncthreads();
+    const unsigned flags = __builtin_amdgcn_readfirstlane(sh.flags);
+    dense_star = (flags & 1u) != 0;
+    closure = (flags & 2u) == 0;
+    // closure row: X_o = Zinv_o (b_o + g X_p) = zr . b_o + dr . b_p with
+    //   dr[w] = g sum_v (row u of Zinv_o)[v] Zinv_p[v][w],
+    // the rows Zinv_p[v] being those of the partner's lanes (e, p, v)
     {
       double dr[T];
+#pragma unroll
+      for (int w = 0; w < T; ++w) dr[w] = 0.0;
       if (gcount == 1 && closure) {
-        double rhs[T];
+        constexpr int per_q = C::kElems * T;
+        double zr[T];
 #pragma unroll
-        for (int v = 0; v < T; ++v) rhs[v] = gcoef * zr[v];
-        zt_solve<T>(sh.G[es][gp][gp], rhs, dr);
-      } else {
+        for (int v = 0; v < T; ++v) zr[v] = sh.zr[tid][v];
 #pragma unroll
-        for (int v = 0; v < T; ++v) dr[v] = 0.0;
+        for (int v = 0; v < T; ++v) {
+          const double cv = gcoef * zr[v];
+#pragma unroll
+          for (int w = 0; w < T; ++w) dr[w] = fma(cv, sh.zr[gp * per_q + es * T + v][w], dr[w]);
+        }
       }
 #pragma unroll
       for (int v = 0; v < T; ++v) sh.dr[tid][v] = dr[v];
+    }
+    maxlevel = 0;
+    mylevel = 0;
+    if (!closure) {
+      // dependency levels of a general upper-triangular E (level = longest
+      // coupling chain below a quantity), one thread per element
+      if (tid < nloc) {
+        int lev[kNQ];
+        int mx = 0;
+#pragma unroll
+        for (int o = kNQ - 1; o >= 0; --o) {
+          int l = 0;
+#pragma unroll
+          for (int q = o + 1; q < kNQ; ++q)
+            if (sh.G[tid][o][q] != 0.0 && lev[q] + 1 > l) l = lev[q] + 1;
+          lev[o] = l;
+          sh.level[tid][o] = l;
+          mx = l > mx ? l : mx;
+        }
+        atomicMax(&sh.maxlevel, mx);
+      }
+      __syncthreads();
+      maxlevel = sh.maxlevel;
+      mylevel = active ? sh.level[es][p] : 0;
     }
   }
 
@@ -529,21 +585,25 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);  // (element, quantity) row of this lane
 
-  // register rows of b below the top block
+  // register rows of b below the top block.  In float64 they are loaded
+  // after the per-element setup (so that its loads do not wait behind them)
+  // and scaled just before the first green update, when they have arrived.
+  constexpr bool kDeferRows = Mode == kInit && std::is_same_v<R, double>;
   R b[C::LR];
-  if constexpr (Mode == kInit) {
+  const double w_u = sinv_w(u);
+  const double* const q0row = a.Q0 + erow * B;
+  if constexpr (Mode == kInit && !kDeferRows) {
     // b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
-    const double w = sinv_w(u);
-    const double* q0row = a.Q0 + erow * B;
 #pragma unroll
-    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w);
-  } else {
+    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w_u);
+  } else if constexpr (Mode == kCorrect) {
     const float* rrow = rin + erow * (B * T) + u;
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(rrow[n * T]);
   }
   // Q0 of the first chunk (top block): its loads are issued before the
-  // per-element setup so that their latency overlaps it
+  // per-element setup so that their latency overlaps it; the registers then
+  // carry each following top-block chunk, loaded one chunk ahead
   constexpr int kFirstC = chunk_size(N, C::kChunk, 0), kFirstM = chunk_start(N, C::kChunk, 0);
   constexpr int kFirstPer = (kE * kNQ * kFirstC + kThreads - 1) / kThreads;
   double q_first[kFirstPer];
@@ -557,6 +617,10 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   }
   LaneSetup<N, R> L;
   L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
+  if constexpr (kDeferRows) {
+#pragma unroll
+    for (int n = 0; n < C::LN; ++n) b[n] = q0row[n];
+  }
   const int pb = C::blk(es, L.gp);  // block of the coupled quantity (own block if uncoupled)
   // Quantities without a diagonal source (E*_pp = 0) solve with Z^-1, whose
   // rows have two non-zeros (columns zc0, zc1 of row u); the dense row u of
@@ -592,18 +656,11 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
         if constexpr (Mode == kInit) {
           constexpr int per_thread = (kE * kNQ * c + kThreads - 1) / kThreads;
           double q[per_thread];
-          if constexpr (decltype(ci)::value == 0) {
-            static_assert(per_thread == kFirstPer && m0 == kFirstM, "first chunk");
+          // chunk 0 was loaded before the setup, the others during the green
+          // update of the chunk before them
+          static_assert(per_thread <= kFirstPer && (decltype(ci)::value > 0 || m0 == kFirstM), "top chunks");
 #pragma unroll
-            for (int k = 0; k < per_thread; ++k) q[k] = q_first[k];
-          } else {
-#pragma unroll
-            for (int k = 0; k < per_thread; ++k) {
-              const int i = tid + k * kThreads;
-              const int ee = i / (kNQ * c), pp = (i / c) % kNQ, kk = i % c;
-              q[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + m0 + kk] : 0.0;
-            }
-          }
+          for (int k = 0; k < per_thread; ++k) q[k] = q_first[k];
 #pragma unroll
           for (int k = 0; k < per_thread; ++k) {
             const int i = tid + k * kThreads;
@@ -783,6 +840,23 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
       //    the chunk stays in bufX until the next chunk's step 2, so the
       //    remaining output groups are read from it here.
       if constexpr (g > 0) {
+        if constexpr (kDeferRows && g == N && decltype(ci)::value == 0) {
+          // b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
+#pragma unroll
+          for (int n = 0; n < C::LN; ++n) b[n] *= w_u;
+        }
+        if constexpr (Mode == kInit && g == N && decltype(ci)::value + 1 < nchunks(N, C::kChunk)) {
+          // Q0 of the next top-block chunk, in flight during this green update
+          constexpr int cn = chunk_size(N, C::kChunk, decltype(ci)::value + 1);
+          constexpr int mn = chunk_start(N, C::kChunk, decltype(ci)::value + 1);
+          constexpr int per_next = (kE * kNQ * cn + kThreads - 1) / kThreads;
+#pragma unroll
+          for (int k = 0; k < per_next; ++k) {
+            const int i = tid + k * kThreads;
+            const int ee = i / (kNQ * cn), pp = (i / cn) % kNQ, kk = i % cn;
+            q_first[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + mn + kk] : 0.0;
+          }
+        }
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
           if constexpr (Mode == kInit && kk == c / 4) {
@@ -1193,14 +1267,16 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
   const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);
   const double w = sinv_w(u);
 
+  // rows below the top block, loaded after the setup so that its loads do
+  // not wait behind them
   R r[C::LR];
+  LaneSetup<N, R> L;
+  L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
   {
     const double* q0row = a.Q0 + erow * B;
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) r[n] = q0row[n] * w;
   }
-  LaneSetup<N, R> L;
-  L.run(sh, a, e0, nloc, tid, es, p, u, active, cb);
   const double zpp = sh.G[es][p][p];
   const bool general_g = __builtin_amdgcn_readfirstlane(__syncthreads_or(active && L.gcount > 1)) != 0;
   const int pb = C::blk(es, L.gp);
