@@ -279,20 +279,35 @@ __device__ __forceinline__ void prefetch_columns(const R* kv, int wave) {
   }
 }
 
+// First coefficient group of column M of the usage-ordered Khat table
+// (possibly partial), issued into `grp` without waiting for it.
+template <int N, int M, typename R>
+__device__ __forceinline__ void load_first_group(const R* kv, R (&grp)[kGroup<R>]) {
+  using P = stp_gen::KhatPattern<N>;
+  constexpr int GS = kGroup<R>;
+  constexpr int count = P::col_count[M];
+  if constexpr (count > 0) load_group<R, P::col_start[M], (count < GS ? count : GS)>(kv, grp);
+}
+
 // b[n] -= Khat^j[n, M] y_j for the non-zeros of column M (usage order of the
 // generated pattern: directions, then rows ascending), in groups of
-// kGroup<R> coefficients; the next group's scalar load is issued before the
-// current group's fused multiply-adds and waited for after them.
-template <int N, int M, typename R>
-__device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y2, const R* kv) {
+// kGroup<R> coefficients.  `cur` arrives holding the column's first group
+// (issued earlier by load_first_group or by the previous column); each
+// group's fused multiply-adds run while the next group's scalar load is in
+// flight, and the last group issues the first group of column MNext (< 0:
+// none), so that a column starts without waiting for its coefficients.
+template <int N, int M, int MNext, typename R>
+__device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y2, const R* kv, R (&cur)[kGroup<R>]) {
   using P = stp_gen::KhatPattern<N>;
   constexpr int GS = kGroup<R>;
   constexpr int start = P::col_start[M];
   constexpr int count = P::col_count[M];
   constexpr int ngroups = (count + GS - 1) / GS;
-  if constexpr (count > 0) {
-    R cur[GS], nxt[GS];
-    load_group<R, start, (count < GS ? count : GS)>(kv, cur);
+  constexpr bool kNext = MNext >= 0 && MNext < Cfg<N>::B;
+  constexpr int next_count = kNext ? P::col_count[kNext ? MNext : 0] : 0;
+  if constexpr (count == 0) {
+    if constexpr (next_count > 0) load_first_group<N, (kNext ? MNext : 0), R>(kv, cur);
+  } else {
 #pragma unroll
     for (int i = 0; i < (count < GS ? count : GS); ++i) use_s(cur[i]);
     static_for<0, ngroups>([&](auto G) __attribute__((always_inline)) {
@@ -301,7 +316,11 @@ __device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y
       constexpr int gn = (start + count - g0) < GS ? (start + count - g0) : GS;
       constexpr int g1 = g0 + GS;
       constexpr int gn1 = (start + count - g1) < GS ? (start + count - g1) : GS;
-      if constexpr (gi + 1 < ngroups) load_group<R, g1, gn1>(kv, nxt);
+      constexpr bool kLast = gi + 1 == ngroups;
+      constexpr int nload = kLast ? (next_count < GS ? next_count : GS) : gn1;
+      R nxt[GS];
+      if constexpr (!kLast) load_group<R, g1, gn1>(kv, nxt);
+      else if constexpr (next_count > 0) load_first_group<N, (kNext ? MNext : 0), R>(kv, nxt);
       static_for<0, gn>([&](auto I) __attribute__((always_inline)) {
         constexpr int e = g0 + decltype(I)::value;
         constexpr int n = P::row[e];
@@ -312,12 +331,16 @@ __device__ __forceinline__ void green_column(R (&b)[Cfg<N>::LR], R y0, R y1, R y
       static_for<0, gn>([&](auto I) __attribute__((always_inline)) {
         pin_v(b[P::row[g0 + decltype(I)::value]]);
       });
-      if constexpr (gi + 1 < ngroups) {
+      if constexpr (!kLast) {
 #pragma unroll
-        for (int i = 0; i < gn1; ++i) {
+        for (int i = 0; i < nload; ++i) {
           use_s(nxt[i]);
           cur[i] = nxt[i];
         }
+      } else if constexpr (nload > 0) {
+        // the next column's first group: handed over without waiting here
+#pragma unroll
+        for (int i = 0; i < nload; ++i) cur[i] = nxt[i];
       }
     });
   }
@@ -347,6 +370,67 @@ __device__ __forceinline__ void stage_rows(R* buf, const Src* src, int64_t e0, i
     if (i < limit) buf[C::blk(row / kNQ, row % kNQ) + r] = static_cast<R>(v[k]);
   }
 }
+
+// The two halves of stage_rows, for callers that overlap the loads with
+// other work: the loads of columns [m0 T, m0 T + PER) into registers, then
+// their stores into the chunk buffer.
+template <int N, int PER>
+struct RowStage {
+  using C = Cfg<N>;
+  static constexpr int kIters = (C::kElems * kNQ * PER + C::kThreads - 1) / C::kThreads;
+  double v[kIters];
+  __device__ __forceinline__ void issue(const double* src, int64_t e0, int m0T, int nloc, int tid) {
+    const int limit = nloc * kNQ * PER;
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) {
+      const int i = tid + k * C::kThreads;
+      const int row = i / PER, r = i % PER;
+      v[k] = i < limit ? src[(e0 * kNQ + row) * (C::B * C::T) + m0T + r] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void commit(double* buf, int nloc, int tid) const {
+    const int limit = nloc * kNQ * PER;
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) {
+      const int i = tid + k * C::kThreads;
+      const int row = i / PER, r = i % PER;
+      if (i < limit) buf[C::blk(row / kNQ, row % kNQ) + r] = v[k];
+    }
+  }
+};
+
+// Q0 of the CM modes starting at m0 of the group, [element][quantity][mode],
+// in the same two halves.
+template <int N, int CM>
+struct Q0Stage {
+  using C = Cfg<N>;
+  static constexpr int kIters = (C::kElems * kNQ * CM + C::kThreads - 1) / C::kThreads;
+  double v[kIters];
+  __device__ __forceinline__ void issue(const double* Q0, int64_t e0, int m0, int nloc, int tid) {
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) {
+      const int i = tid + k * C::kThreads;
+      v[k] = i < nloc * kNQ * CM ? Q0[(e0 * kNQ + i / CM) * C::B + m0 + i % CM] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void commit(double* buf, int nloc, int tid) const {
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) {
+      const int i = tid + k * C::kThreads;
+      if (i < nloc * kNQ * CM) buf[i] = v[k];
+    }
+  }
+};
+
+// Position of chunk ci of degree block g in the chunk order (blocks from N
+// down, chunks ascending), and the chunk that follows it.
+__host__ __device__ constexpr int chunk_index(int N, int g, int ci, int cmax) {
+  int s = 0;
+  for (int h = N; h > g; --h) s += nchunks(h, cmax);
+  return s + ci;
+}
+__host__ __device__ constexpr int next_block(int g, int ci, int cmax) { return ci + 1 < nchunks(g, cmax) ? g : g - 1; }
+__host__ __device__ constexpr int next_chunk(int g, int ci, int cmax) { return ci + 1 < nchunks(g, cmax) ? ci + 1 : 0; }
 
 // Modes of the solve kernel.
 constexpr int kInit = 0;     // b = Q0 (S^-1 w); Q <- X
@@ -585,9 +669,10 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);  // (element, quantity) row of this lane
 
-  // register rows of b below the top block.  In float64 they are loaded
-  // after the per-element setup (so that its loads do not wait behind them)
-  // and scaled just before the first green update, when they have arrived.
+  // register rows of b below the top block.  In float64 and in the
+  // correction mode they are loaded after the per-element setup (so that its
+  // loads do not wait behind them); the float64 rows are scaled just before
+  // the first green update, when they have arrived.
   constexpr bool kDeferRows = Mode == kInit && std::is_same_v<R, double>;
   R b[C::LR];
   const double w_u = sinv_w(u);
@@ -596,10 +681,6 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
     // b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w_u);
-  } else if constexpr (Mode == kCorrect) {
-    const float* rrow = rin + erow * (B * T) + u;
-#pragma unroll
-    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(rrow[n * T]);
   }
   // Q0 of the first chunk (top block): its loads are issued before the
   // per-element setup so that their latency overlaps it; the registers then
@@ -620,6 +701,12 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   if constexpr (kDeferRows) {
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) b[n] = q0row[n];
+  } else if constexpr (Mode == kCorrect) {
+    // the residual rows below the top block (after the setup, like the rows
+    // of the float64 solve)
+    const float* rrow = rin + erow * (B * T) + u;
+#pragma unroll
+    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(rrow[n * T]);
   }
   const int pb = C::blk(es, L.gp);  // block of the coupled quantity (own block if uncoupled)
   // Quantities without a diagonal source (E*_pp = 0) solve with Z^-1, whose
@@ -857,6 +944,8 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
             q_first[k] = (ee < nloc) ? a.Q0[((e0 + ee) * kNQ + pp) * B + mn + kk] : 0.0;
           }
         }
+        R kgrp[kGroup<R>];
+        load_first_group<N, m0, R>(kv, kgrp);
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
           if constexpr (Mode == kInit && kk == c / 4) {
@@ -865,7 +954,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
           }
           R y0, y1, y2;
           L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
-          green_column<N, m0 + kk, R>(b, y0, y1, y2, kv);
+          green_column<N, m0 + kk, (kk + 1 < c ? m0 + kk + 1 : -1), R>(b, y0, y1, y2, kv, kgrp);
           // keep the scheduler from hoisting the next mode's LDS reads
           __builtin_amdgcn_sched_barrier(0);
         });
@@ -1248,12 +1337,21 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
   using R = double;
   constexpr int B = C::B, T = C::T, kE = C::kElems, kThreads = C::kThreads;
   __shared__ Shared<N, R> sh;
-  R* const bufX = sh.u.c.bufX;  // Q of the chunk
   R* const bufR = sh.u.c.bufB;  // residual of the chunk, same layout, to memory after the chunk
-  // Q0 of a top-block chunk, [element][quantity][mode]; the per-lane rows of
-  // the setup are not used after it
-  double* const q0s = &sh.zr[0][0];
-  static_assert(C::kSlots * kNQ * C::kChunk <= C::kThreads * T, "Q0 staging fits");
+  // Q of the chunks (and Q0 of the top-block chunks, [element][quantity][mode])
+  // alternate between two buffers: the X chunk buffer and the per-lane rows
+  // of the setup, which are not used after it.  Each chunk's loads are issued
+  // during the previous chunk and stored to its buffer before that chunk's
+  // green update, so only the first chunk waits for memory.  Where the second
+  // buffer does not fit, every chunk stages its own rows.
+  constexpr int kXSize = C::kSlots * kNQ * C::S, kQ0Size = C::kSlots * kNQ * C::kChunk;
+  constexpr bool kTwoBuffers = kXSize + 2 * kQ0Size <= 2 * C::kThreads * T;
+  static_assert(kQ0Size <= C::kThreads * T, "Q0 staging fits");
+  double* const rows = &sh.zr[0][0];  // zr and dr: 2 kThreads T contiguous doubles
+  auto xbuf = [&](int ci_index) -> R* { return (kTwoBuffers && (ci_index & 1)) ? rows : sh.u.c.bufX; };
+  auto q0buf = [&](int ci_index) -> double* {
+    return kTwoBuffers ? rows + kXSize + (ci_index & 1) * kQ0Size : rows;
+  };
   const int tid = threadIdx.x;
   const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kE;
   const int64_t nloc64 = a.n - e0 < kE ? a.n - e0 : kE;
@@ -1289,16 +1387,33 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
     static_for<0, nchunks(g, C::kChunk)>([&](auto ci) __attribute__((always_inline)) {
       constexpr int m0 = chunk_start(g, C::kChunk, decltype(ci)::value);
       constexpr int c = chunk_size(g, C::kChunk, decltype(ci)::value);
+      constexpr int CI = chunk_index(N, g, decltype(ci)::value, C::kChunk);
+      R* const bufX = xbuf(CI);
+      double* const q0s = q0buf(CI);
       if constexpr (g > 0) prefetch_columns<N, R, m0, c, kThreads / 64>(kv, wave);
-      // stage Q of the chunk (and Q0 of the top block) in LDS, coalesced
-      {
+      // stage Q of the chunk (and Q0 of the top block) in LDS, coalesced,
+      // unless the previous chunk did
+      if constexpr (!kTwoBuffers || CI == 0) {
         stage_rows<N, R, c * T>(bufX, static_cast<const double*>(a.Q), e0, m0 * T, nloc, tid);
         if constexpr (g == N) {
-          for (int i = tid; i < nloc * kNQ * c; i += kThreads)
-            q0s[i] = a.Q0[(e0 * kNQ + i / c) * B + m0 + i % c];
+          Q0Stage<N, c> qs;
+          qs.issue(a.Q0, e0, m0, nloc, tid);
+          qs.commit(q0s, nloc, tid);
         }
       }
       __syncthreads();
+      // loads of the next chunk, in flight during the local terms
+      constexpr bool kHasNext = !(g == 0 && decltype(ci)::value + 1 == nchunks(g, C::kChunk));
+      constexpr int gn = kHasNext ? next_block(g, decltype(ci)::value, C::kChunk) : 0;
+      constexpr int cin = kHasNext ? next_chunk(g, decltype(ci)::value, C::kChunk) : 0;
+      constexpr int mn = chunk_start(gn, C::kChunk, cin), cn = chunk_size(gn, C::kChunk, cin);
+      constexpr bool kPrefetch = kTwoBuffers && kHasNext;
+      RowStage<N, cn * T> nrows;
+      Q0Stage<N, cn> nq0;
+      if constexpr (kPrefetch) {
+        nrows.issue(static_cast<const double*>(a.Q), e0, mn * T, nloc, tid);
+        if constexpr (gn == N) nq0.issue(a.Q0, e0, mn, nloc, tid);
+      }
       // local terms of the chunk's rows: their residual is now complete
       static_for<0, c>([&](auto k) __attribute__((always_inline)) {
         constexpr int kk = decltype(k)::value;
@@ -1320,13 +1435,21 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
         }
         bufR[cb + kk * T + u] = base - zx + ex;
       });
+      // the next chunk's rows to the other buffer (no wave reads it during
+      // this chunk)
+      if constexpr (kPrefetch) {
+        nrows.commit(xbuf(CI + 1), nloc, tid);
+        if constexpr (gn == N) nq0.commit(q0buf(CI + 1), nloc, tid);
+      }
       // Khat term into the rows of lower blocks
       if constexpr (g > 0) {
+        R kgrp[kGroup<R>];
+        load_first_group<N, m0, R>(kv, kgrp);
         static_for<0, c>([&](auto k) __attribute__((always_inline)) {
           constexpr int kk = decltype(k)::value;
           R y0, y1, y2;
           L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
-          green_column<N, m0 + kk, R>(r, y0, y1, y2, kv);
+          green_column<N, m0 + kk, (kk + 1 < c ? m0 + kk + 1 : -1), R>(r, y0, y1, y2, kv, kgrp);
           __builtin_amdgcn_sched_barrier(0);
         });
       }
