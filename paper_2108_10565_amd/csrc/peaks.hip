@@ -23,6 +23,8 @@ constexpr int kChains = 16;
 constexpr int kMfmaAcc = 8;
 constexpr int kFmaIters = 65536;
 constexpr int kMfmaIters = 8192;
+constexpr int kMfmaUnroll = 16;
+static_assert(kMfmaIters % kMfmaUnroll == 0, "whole unrolled bodies");
 constexpr size_t kOutBytes = static_cast<size_t>(kPeakBlocks) * kPeakThreads * sizeof(double);
 
 template <typename F>
@@ -47,9 +49,16 @@ __global__ __launch_bounds__(kPeakThreads) void mfma_f64_loop(double a, double b
 #pragma unroll
   for (int k = 0; k < kMfmaAcc; ++k) acc[k] = v4d{0.0, 0.0, 0.0, 0.0};
   const double av = a + 1e-9 * threadIdx.x;
-  for (int i = 0; i < iters; ++i) {
+  // unrolled by kMfmaUnroll (iters is a multiple of it): the compiler keeps
+  // the accumulators in the matrix-core registers across a whole unrolled
+  // body and copies them to and from the vector registers only at the loop
+  // back-edge, which a rolled loop does on every iteration
+  for (int i = 0; i < iters; i += kMfmaUnroll) {
 #pragma unroll
-    for (int k = 0; k < kMfmaAcc; ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[k], 0, 0, 0);
+    for (int r = 0; r < kMfmaUnroll; ++r) {
+#pragma unroll
+      for (int k = 0; k < kMfmaAcc; ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[k], 0, 0, 0);
+    }
   }
   double s = 0.0;
 #pragma unroll
