@@ -446,6 +446,10 @@ struct LaneSetup {
   using C = Cfg<N>;
   R sa0[kStarNnz], sa1[kStarNnz], sa2[kStarNnz];
   int sq[kStarNnz];
+  // LDS addresses of the star-row entries in one fixed chunk buffer (bind):
+  // the reads of each mode then take the mode's offset as an immediate
+  using LdsR = __attribute__((address_space(3))) const R;
+  LdsR* sp[kStarNnz];
   int gp, gcount;
   double gcoef;
   bool dense_star, closure;
@@ -616,6 +620,29 @@ struct LaneSetup {
     }
   }
 
+  __device__ __forceinline__ void bind(const R* buf) {
+#pragma unroll
+    for (int k = 0; k < kStarNnz; ++k) sp[k] = (LdsR*)buf + sq[k];
+  }
+  // star() for the buffer given to bind(): no address arithmetic per mode
+  template <int kk>
+  __device__ __forceinline__ void star_bound(const R* bufX, const PredictArgs& a, int64_t e0, int es, int p, int u,
+                                             bool active, R& y0, R& y1, R& y2) const {
+    constexpr int T = C::T;
+    y0 = y1 = y2 = R(0);
+    if (!dense_star) {
+#pragma unroll
+      for (int k = 0; k < kStarNnz; ++k) {
+        const R xq = sp[k][kk * T];
+        y0 = fma(sa0[k], xq, y0);
+        y1 = fma(sa1[k], xq, y1);
+        y2 = fma(sa2[k], xq, y2);
+      }
+    } else {
+      star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
+    }
+  }
+
   // y_j = (A^{j*} X[:, m, u])_p for j = 1..3 from the chunk buffer
   template <int kk>
   __device__ __forceinline__ void star(const R* bufX, const PredictArgs& a, int64_t e0, int es, int p, int u,
@@ -709,6 +736,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
     for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(rrow[n * T]);
   }
   const int pb = C::blk(es, L.gp);  // block of the coupled quantity (own block if uncoupled)
+  if constexpr (std::is_same_v<R, double>) L.bind(bufX);
   // Quantities without a diagonal source (E*_pp = 0) solve with Z^-1, whose
   // rows have two non-zeros (columns zc0, zc1 of row u); the dense row u of
   // (Z - E*_pp I)^-1 and the closure row dr are read only by waves holding a
@@ -953,7 +981,12 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
             __builtin_amdgcn_sched_barrier(0);
           }
           R y0, y1, y2;
-          L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
+          // float64: the star reads take the mode offset as an immediate
+          // (measured 2.3% faster); the float chain (and the residual
+          // kernel) keep the per-mode address arithmetic, the bound form
+          // having measured slower there
+          if constexpr (std::is_same_v<R, double>) L.template star_bound<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
+          else L.template star<kk>(bufX, a, e0, es, p, u, active, y0, y1, y2);
           green_column<N, m0 + kk, (kk + 1 < c ? m0 + kk + 1 : -1), R>(b, y0, y1, y2, kv, kgrp);
           // keep the scheduler from hoisting the next mode's LDS reads
           __builtin_amdgcn_sched_barrier(0);
