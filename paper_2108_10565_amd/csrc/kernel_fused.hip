@@ -92,6 +92,15 @@ __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (End > Begin) static_for_impl<Begin>(f, std::make_integer_sequence<int, End - Begin>{});
 }
 
+// Smallest S >= len with nq S = t (mod 16) (nq odd), or the smallest odd
+// S >= len (nq even, where no such S exists for odd t).
+__host__ __device__ constexpr int stride_for(int len, int t, int nq) {
+  for (int s = len; s < len + 32; ++s) {
+    if (nq % 2 == 1 ? ((nq * s - t) % 16 + 16) % 16 == 0 : s % 2 == 1) return s;
+  }
+  return len;
+}
+
 template <int N>
 struct Cfg {
   static constexpr int B = n_modes(N);
@@ -106,16 +115,23 @@ struct Cfg {
   static constexpr int kThreads = (kElems * kCols + 63) / 64 * 64;
   static constexpr int kSlots = kElems + 1;        // + one dummy slot for spare lanes
   static constexpr int kChunk = kChunkMax < DN ? kChunkMax : DN;
-  // Stride (doubles) of one (element, quantity) block of the chunk buffers,
-  // padded so that S = T (mod 16): with the quantity-major block order the
-  // LDS address of lane (e, p, u) is then congruent to its lane index modulo
-  // 16 doubles, so the column-wise accesses of 16 consecutive lanes cover one
-  // 128-byte span of the banks without a conflict.
+  // The chunk buffers hold one block of S doubles per (element, quantity) row
+  // in the order of the rows in memory (element-major), so a row's block is
+  // row * S: the output passes address LDS and memory from the same row
+  // index.  S is padded so that kNQ S = T (mod 16) when kNQ is odd: the LDS
+  // address of lane (e, p, u) (lanes quantity-major) is then congruent to the
+  // lane index modulo 16 doubles, 13 S = 7 making S = 3 = kElems T at N = 6,
+  // so 16 consecutive lanes cover one 128-byte span of the banks without a
+  // conflict.  One extra block at the end takes the writes of the spare lanes
+  // past the last element (their values are never read back).
   static constexpr int kChunkT = kChunk * T;
-  static constexpr int S = kChunkT + (((T - kChunkT) % 16) + 16) % 16;
-  // Offset of the (element slot e, quantity q) block: quantity-major, so the
-  // lanes of one quantity (consecutive e, u) address consecutive runs of T.
-  static __device__ __forceinline__ int blk(int e, int q) { return (q * kSlots + e) * S; }
+  static constexpr int S = stride_for(kChunkT, T, kNQ);
+  static constexpr int kRows = kElems * kNQ;       // real blocks
+  static constexpr int kBufSize = (kRows + 1) * S; // + the spare lanes' block
+  // Offset of the block of row `row` = element * kNQ + quantity; rows past
+  // the last element (spare lanes, the dummy slot) share the last block.
+  static __device__ __forceinline__ int rowblk(int row) { return (row < kRows ? row : kRows) * S; }
+  static __device__ __forceinline__ int blk(int e, int q) { return rowblk(e * kNQ + q); }
 };
 
 // Degree block g is processed in nchunks(g) chunks of near-equal size.
@@ -164,8 +180,8 @@ struct Shared {
   union {
     double A[C::kSlots][3][kNQ][kNQ];       // setup only: A^{j*} = dt A^j
     struct {
-      R bufB[C::kSlots * kNQ * C::S];       // b of the chunk: [p][e] blocks of [chunk][T], stride S
-      R bufX[C::kSlots * kNQ * C::S];       // X of the chunk, same layout
+      R bufB[C::kBufSize];                  // b of the chunk: [e][p] blocks of [chunk][T], stride S
+      R bufX[C::kBufSize];                  // X of the chunk, same layout
     } c;
   } u;
 };
@@ -367,7 +383,7 @@ __device__ __forceinline__ void stage_rows(R* buf, const Src* src, int64_t e0, i
   for (int k = 0; k < kIters; ++k) {
     const int i = tid + k * C::kThreads;
     const int row = i / PER, r = i % PER;
-    if (i < limit) buf[C::blk(row / kNQ, row % kNQ) + r] = static_cast<R>(v[k]);
+    if (i < limit) buf[C::rowblk(row) + r] = static_cast<R>(v[k]);
   }
 }
 
@@ -394,7 +410,7 @@ struct RowStage {
     for (int k = 0; k < kIters; ++k) {
       const int i = tid + k * C::kThreads;
       const int row = i / PER, r = i % PER;
-      if (i < limit) buf[C::blk(row / kNQ, row % kNQ) + r] = v[k];
+      if (i < limit) buf[C::rowblk(row) + r] = v[k];
     }
   }
 };
@@ -696,19 +712,14 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int64_t erow = ((active ? e0 + es : 0) * kNQ + p);  // (element, quantity) row of this lane
 
-  // register rows of b below the top block.  In float64 and in the
-  // correction mode they are loaded after the per-element setup (so that its
-  // loads do not wait behind them); the float64 rows are scaled just before
-  // the first green update, when they have arrived.
+  // register rows of b below the top block, loaded after the per-element
+  // setup (so that its loads do not wait behind them and its elimination
+  // does not compete with them for registers); the float64 rows are scaled
+  // just before the first green update, when they have arrived.
   constexpr bool kDeferRows = Mode == kInit && std::is_same_v<R, double>;
   R b[C::LR];
   const double w_u = sinv_w(u);
   const double* const q0row = a.Q0 + erow * B;
-  if constexpr (Mode == kInit && !kDeferRows) {
-    // b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu)
-#pragma unroll
-    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w_u);
-  }
   // Q0 of the first chunk (top block): its loads are issued before the
   // per-element setup so that their latency overlaps it; the registers then
   // carry each following top-block chunk, loaded one chunk ahead
@@ -728,6 +739,10 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
   if constexpr (kDeferRows) {
 #pragma unroll
     for (int n = 0; n < C::LN; ++n) b[n] = q0row[n];
+  } else if constexpr (Mode == kInit) {
+    // b[p, n, u] = Q0[p, n] (S^-1 w)_u (eq:b_pmu), converted on arrival
+#pragma unroll
+    for (int n = 0; n < C::LN; ++n) b[n] = static_cast<R>(q0row[n] * w_u);
   } else if constexpr (Mode == kCorrect) {
     // the residual rows below the top block (after the setup, like the rows
     // of the float64 solve)
@@ -901,11 +916,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
         const int limit = nloc * kNQ * per;
         double* Qg = a.Q + e0 * (kNQ * B * T) + m0 * T;
         // value k of this lane: run index i = tid + k kThreads -> (row, r)
-        auto lds_index = [&](int i) __attribute__((always_inline)) {
-          const int row = i / per;
-          const int ee = row / kNQ;
-          return C::blk(ee < kE ? ee : kE, row % kNQ) + i % per;
-        };
+        auto lds_index = [&](int i) __attribute__((always_inline)) { return C::rowblk(i / per) + i % per; };
         // streaming stores: Q is written once and not read again here, so
         // it should not displace the Khat lines in L2
         auto store_groups = [&](int glo, int ghi) __attribute__((always_inline)) {
@@ -945,8 +956,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_solve_kernel(PredictAr
           for (int k = 0; k < kInt; ++k) {
             const int j = tid + k * kThreads;
             const int row = j / c, kk = j % c;
-            const int ee = row / kNQ, pp = row % kNQ;
-            double v = a.dt * static_cast<double>(bufX[C::blk(ee < kE ? ee : kE, pp) + kk * T]);
+            double v = a.dt * static_cast<double>(bufX[C::rowblk(row) + kk * T]);
             if constexpr (Mode == kCorrect) v += j < ilimit ? Ig[row * B + m0 + kk] : 0.0;
             if (j < ilimit) __builtin_nontemporal_store(v, &Ig[row * B + m0 + kk]);
           }
@@ -1254,11 +1264,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void mfma_solve_kernel(PredictArg
         constexpr int per = c * T;
         const int limit = nloc * kNQ * per;
         double* Qg = a.Q + e0 * (kNQ * B * T) + m0 * T;
-        auto lds_index = [&](int i) __attribute__((always_inline)) {
-          const int row = i / per;
-          const int ee = row / kNQ;
-          return C::blk(ee < kE ? ee : kE, row % kNQ) + i % per;
-        };
+        auto lds_index = [&](int i) __attribute__((always_inline)) { return C::rowblk(i / per) + i % per; };
         {
           constexpr int kOutGroup = 3;
           constexpr int nOut = (kOut + kOutGroup - 1) / kOutGroup;
@@ -1286,8 +1292,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void mfma_solve_kernel(PredictArg
           for (int k = 0; k < kInt; ++k) {
             const int j = tid + k * kThreads;
             const int row = j / c, kk = j % c;
-            const int ee = row / kNQ, pp = row % kNQ;
-            double v = a.dt * static_cast<double>(bufX[C::blk(ee < kE ? ee : kE, pp) + kk * T]);
+            double v = a.dt * static_cast<double>(bufX[C::rowblk(row) + kk * T]);
             if constexpr (Mode == kCorrect) v += j < ilimit ? Ig[row * B + m0 + kk] : 0.0;
             if (j < ilimit) __builtin_nontemporal_store(v, &Ig[row * B + m0 + kk]);
           }
@@ -1377,7 +1382,7 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
   // during the previous chunk and stored to its buffer before that chunk's
   // green update, so only the first chunk waits for memory.  Where the second
   // buffer does not fit, every chunk stages its own rows.
-  constexpr int kXSize = C::kSlots * kNQ * C::S, kQ0Size = C::kSlots * kNQ * C::kChunk;
+  constexpr int kXSize = C::kBufSize, kQ0Size = C::kSlots * kNQ * C::kChunk;
   constexpr bool kTwoBuffers = kXSize + 2 * kQ0Size <= 2 * C::kThreads * T;
   static_assert(kQ0Size <= C::kThreads * T, "Q0 staging fits");
   double* const rows = &sh.zr[0][0];  // zr and dr: 2 kThreads T contiguous doubles
@@ -1504,14 +1509,12 @@ __global__ __launch_bounds__(Cfg<N>::kThreads) void fused_residual_kernel(Predic
 #pragma unroll
           for (int k = 0; k < kGroupOut; ++k) {
             const int i = tid + (gi * kGroupOut + k) * kThreads;
-            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-            v[k] = static_cast<float>(bufR[C::blk(ee < kE ? ee : kE, rem / per) + rem % per]);
+            v[k] = static_cast<float>(bufR[C::rowblk(i / per) + i % per]);
           }
 #pragma unroll
           for (int k = 0; k < kGroupOut; ++k) {
             const int i = tid + (gi * kGroupOut + k) * kThreads;
-            const int ee = i / (kNQ * per), rem = i % (kNQ * per);
-            if (i < limit) __builtin_nontemporal_store(v[k], &Rg[(ee * kNQ + rem / per) * (B * T) + rem % per]);
+            if (i < limit) __builtin_nontemporal_store(v[k], &Rg[(i / per) * (B * T) + i % per]);
           }
         }
       }
